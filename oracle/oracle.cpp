@@ -1,0 +1,417 @@
+// CPU oracle for the spin-1/2 / spin-1 time-dependent Schroedinger solver of
+// arXiv:2204.05586 ("Spinsim").
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, scalar reference
+// that the GPU path is checked against.  Only the tests, the smoke check and
+// the benchmark's CPU-baseline leg may load it.  It shares no code, header,
+// constant or helper with the GPU library: it parses the same field-program
+// data format with its own structures.
+//
+// Every step follows the paper in its own order and notation:
+//   * CF4 step (Sec. "Unitary time evolution and the Magnus expansion",
+//     eqs. cf4_sample_1, cf4_sample_2, cf4_implementation):
+//     Gauss nodes t_{1,2} = t + (1 -/+ 1/sqrt 3) dt / 2, weights
+//     w_{+/-} = (3 +/- 2 sqrt 3) / 12, u = exp(-i Hbar_2 dt) exp(-i Hbar_1 dt).
+//   * Spin-1/2 exponential: analytic SU(2) form (Sec. "Lie-Trotter based
+//     exponentiator"; the formula itself is not printed, the textbook
+//     exp(-i theta.sigma/2) = cos(|theta|/2) I - i sin(|theta|/2) n.sigma is used).
+//   * Spin-1 exponential: Lie-Trotter with the symmetric (leapfrog) split
+//     T = exp(-i D/2) exp(-i Phi J_phi) exp(-i D/2), n = 2^tau, written
+//     element-wise (eq. lie_trotter_4, with its two misprints corrected:
+//     T_13 carries exp(-i q/6) inside the square and T_22 = cos(Phi) exp(2iq/3)),
+//     built as the residual a = T - I with expm1-style diagonals, then tau
+//     residual squarings a <- (a + 2I) a, then I + a.
+//   * Dynamic rotating frame (Sec. "Dynamically rotating frame"):
+//     omega_r = omega_z(t_k + Dt/2); within an interval the transverse field
+//     is rotated by exp(-i omega_r (t - t_k)) and omega_z -> omega_z - omega_r;
+//     on exit U_k = R(-Dt) U_k^r = diag(exp(-i m omega_r Dt)) U_k^r
+//     (eq. exit_rotating_frame).
+//   * Discretisation (Sec. "Discretization and parallelization"): t_k =
+//     t_start + k Dt, L fine steps of dt = Dt / L per interval, each U_k the
+//     ordered product of its fine steps, and the state series
+//     psi_{k+1} = U_k psi_k (eq. integration_compilation) computed
+//     sequentially, as the paper's CPU state compiler does.
+//
+// Floating point: compiled with -ffp-contract=off on a baseline x86-64
+// target, so no multiply-add is ever fused.  Node times and phase arguments
+// are formed as t_k = t_start + (k * Dt), tau_i = (l + c_i) * dt,
+// t_i = t_k + tau_i and phase = 2 pi * (f * t) + phi.
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include <omp.h>
+
+namespace {
+
+// ---- problem description (own copy of the field-program data format) ------
+struct OTerm {
+  int32_t kind, comp;
+  int32_t a_slot, f_slot, phi_slot;
+  int32_t n_seg, seg_a_slot, seg_phi_slot;
+  double a, f, phi;
+  double t_on, t_off;
+  double seg_t0, seg_len;
+};
+
+struct OProblem {
+  int32_t spin_twice;  // 1: spin-1/2, 2: spin-1
+  int32_t n_terms;
+  int32_t n_fine;      // L
+  int32_t n_squares;   // tau
+  int32_t rotating_frame;
+  int32_t n_params;
+  int64_t n_samples;   // K
+  double t_start;
+  double dt_out;       // Dt
+  const OTerm* terms;
+};
+
+enum { K_CONST = 0, K_COS = 1, K_SIN = 2, K_PWC = 3, K_PWC_COS = 4, K_PWC_SIN = 5 };
+
+template <class R> using cx = std::complex<R>;
+
+template <class R> R two_pi() { return R(2) * std::acos(R(-1)); }
+
+template <class R> cx<R> expi(R x) { return cx<R>(std::cos(x), std::sin(x)); }
+
+// ---- field program ---------------------------------------------------------
+template <class R>
+R param_or(const R* params, int32_t slot, double literal) {
+  return slot >= 0 ? params[slot] : R(literal);
+}
+
+template <class R>
+R phase(R f, R t, R phi) {
+  R ft = f * t;
+  R x = two_pi<R>() * ft;
+  return x + phi;
+}
+
+template <class R>
+int64_t segment(const OTerm& tm, R t) {
+  R x = (t - R(tm.seg_t0)) / R(tm.seg_len);
+  R fl = std::floor(x);
+  int64_t s;
+  if (fl < R(0)) s = 0;
+  else if (fl > R(tm.n_seg - 1)) s = tm.n_seg - 1;
+  else s = (int64_t)fl;
+  return s;
+}
+
+// Field functions f_j(t) in Hz, j = x, y, z, q.  Terms are summed in list order.
+template <class R>
+void field(const OProblem& p, const R* params, R t, R out[4]) {
+  for (int j = 0; j < 4; ++j) out[j] = R(0);
+  for (int i = 0; i < p.n_terms; ++i) {
+    const OTerm& tm = p.terms[i];
+    if (!(R(tm.t_on) < t && t < R(tm.t_off))) continue;
+    R v = R(0);
+    R amp = param_or(params, tm.a_slot, tm.a);
+    R fr = param_or(params, tm.f_slot, tm.f);
+    R ph = param_or(params, tm.phi_slot, tm.phi);
+    if (tm.kind == K_PWC || tm.kind == K_PWC_COS || tm.kind == K_PWC_SIN) {
+      int64_t s = segment(tm, t);
+      if (tm.seg_a_slot >= 0) amp = params[tm.seg_a_slot + s];
+      if (tm.seg_phi_slot >= 0) ph = params[tm.seg_phi_slot + s];
+    }
+    switch (tm.kind) {
+      case K_CONST: case K_PWC: v = amp; break;
+      case K_COS: case K_PWC_COS: v = amp * std::cos(phase(fr, t, ph)); break;
+      case K_SIN: case K_PWC_SIN: v = amp * std::sin(phase(fr, t, ph)); break;
+      default: v = R(0); break;
+    }
+    out[tm.comp] = out[tm.comp] + v;
+  }
+}
+
+// ---- small dense complex matrices -----------------------------------------
+template <class R, int N>
+struct Mat {
+  cx<R> m[N][N];
+  static Mat identity() {
+    Mat r;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) r.m[i][j] = cx<R>(i == j ? R(1) : R(0), R(0));
+    return r;
+  }
+};
+
+template <class R, int N>
+Mat<R, N> matmul(const Mat<R, N>& A, const Mat<R, N>& B) {
+  Mat<R, N> C;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      cx<R> s(0, 0);
+      for (int k = 0; k < N; ++k) s += A.m[i][k] * B.m[k][j];
+      C.m[i][j] = s;
+    }
+  return C;
+}
+
+// ---- exponentiators ---------------------------------------------------------
+// Spin-1/2: exp(-i (theta_x J_x + theta_y J_y + theta_z J_z)), J = sigma / 2.
+template <class R>
+Mat<R, 2> exp_half(const R th[3]) {
+  R big = std::sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+  if (big == R(0)) return Mat<R, 2>::identity();
+  R c = std::cos(big / R(2));
+  R s = std::sin(big / R(2)) / big;
+  Mat<R, 2> e;
+  e.m[0][0] = cx<R>(c, -s * th[2]);
+  e.m[0][1] = cx<R>(-s * th[1], -s * th[0]);
+  e.m[1][0] = cx<R>(s * th[1], -s * th[0]);
+  e.m[1][1] = cx<R>(c, s * th[2]);
+  return e;
+}
+
+// e^{i beta} - 1 without cancellation.
+template <class R>
+cx<R> expim1(R beta) {
+  R h = std::sin(beta / R(2));
+  return cx<R>(R(-2) * h * h, std::sin(beta));
+}
+
+// Residual a = T - I of the symmetric Lie-Trotter factor for the step angles
+// theta = (theta_x, theta_y, theta_z, theta_q) and n = 2^tau.
+template <class R>
+Mat<R, 3> lie_trotter_residual(const R th[4], int tau) {
+  const R n = std::ldexp(R(1), tau);
+  const R z = th[2] / n;
+  const R q = th[3] / n;
+  const R Phi = std::hypot(th[0], th[1]) / n;
+  const R phi = std::atan2(th[1], th[0]);
+  const R C = std::cos(Phi / R(2));
+  const R S = std::sin(Phi / R(2));
+  const R sPhi = std::sin(Phi);
+  const R r = R(1) / std::sqrt(R(2));
+  (void)C;
+  const cx<R> mi(R(0), R(-1));
+  const cx<R> off = mi * cx<R>(r * sPhi, R(0));  // (-i / sqrt 2) sin(Phi)
+  Mat<R, 3> a;
+  // off-diagonal entries of T (eq. lie_trotter_4, corrected)
+  a.m[0][1] = off * expi(q / R(6)) * expi(-z / R(2)) * expi(-phi);
+  a.m[1][0] = off * expi(q / R(6)) * expi(-z / R(2)) * expi(phi);
+  a.m[1][2] = off * expi(q / R(6)) * expi(z / R(2)) * expi(-phi);
+  a.m[2][1] = off * expi(q / R(6)) * expi(z / R(2)) * expi(phi);
+  {
+    cx<R> w = cx<R>(S, R(0)) * expi(-q / R(6)) * expi(-phi);
+    a.m[0][2] = -(w * w);
+    cx<R> v = cx<R>(S, R(0)) * expi(-q / R(6)) * expi(phi);
+    a.m[2][0] = -(v * v);
+  }
+  // diagonal entries of T - I: T_11 = C^2 e^{i b1}, T_22 = cos(Phi) e^{i b2},
+  // T_33 = C^2 e^{i b3}; T_jj - 1 = (e^{i b} - 1) - k S^2 e^{i b}, k = 1, 2, 1.
+  const R b1 = -z - q / R(3);
+  const R b2 = R(2) * q / R(3);
+  const R b3 = z - q / R(3);
+  const R S2 = S * S;
+  a.m[0][0] = expim1(b1) - cx<R>(S2, R(0)) * expi(b1);
+  a.m[1][1] = expim1(b2) - cx<R>(R(2) * S2, R(0)) * expi(b2);
+  a.m[2][2] = expim1(b3) - cx<R>(S2, R(0)) * expi(b3);
+  return a;
+}
+
+// Spin-1: exp(-i (theta_x J_x + theta_y J_y + theta_z J_z + theta_q Q)) by
+// T^(2^tau), squared through the residual a = T - I.
+template <class R>
+Mat<R, 3> exp_one(const R th[4], int tau) {
+  Mat<R, 3> a = lie_trotter_residual(th, tau);
+  for (int s = 0; s < tau; ++s) {
+    Mat<R, 3> b = a;
+    for (int i = 0; i < 3; ++i) b.m[i][i] += cx<R>(R(2), R(0));
+    a = matmul(b, a);
+  }
+  for (int i = 0; i < 3; ++i) a.m[i][i] += cx<R>(R(1), R(0));
+  return a;
+}
+
+template <class R, int N> struct Exp;
+template <class R> struct Exp<R, 2> {
+  static Mat<R, 2> apply(const R th[4], int) { return exp_half(th); }
+};
+template <class R> struct Exp<R, 3> {
+  static Mat<R, 3> apply(const R th[4], int tau) { return exp_one(th, tau); }
+};
+
+// magnetic quantum numbers m = s, ..., -s of the basis states
+template <class R> R mval(int N, int i) { return N == 2 ? (i == 0 ? R(0.5) : R(-0.5)) : R(1 - i); }
+
+// ---- one output interval -----------------------------------------------------
+template <class R, int N>
+Mat<R, N> interval_operator(const OProblem& p, const R* params, int64_t k) {
+  const R sq3 = std::sqrt(R(3));
+  const R c1 = (R(1) - R(1) / sq3) / R(2);
+  const R c2 = (R(1) + R(1) / sq3) / R(2);
+  const R wp = (R(3) + R(2) * sq3) / R(12);
+  const R wm = (R(3) - R(2) * sq3) / R(12);
+  const R Dt = R(p.dt_out);
+  const R dt = Dt / R(p.n_fine);
+  const R tk = R(p.t_start) + R(k) * Dt;
+  R wr = R(0);
+  if (p.rotating_frame) {
+    R f[4];
+    field<R>(p, params, tk + Dt / R(2), f);
+    wr = two_pi<R>() * f[2];
+  }
+  Mat<R, N> U = Mat<R, N>::identity();
+  for (int l = 0; l < p.n_fine; ++l) {
+    R w[2][4];
+    const R cnode[2] = {c1, c2};
+    for (int i = 0; i < 2; ++i) {
+      const R tau_i = (R(l) + cnode[i]) * dt;
+      R f[4];
+      field<R>(p, params, tk + tau_i, f);
+      for (int j = 0; j < 4; ++j) w[i][j] = two_pi<R>() * f[j];
+      // rotating frame: transverse field rotated by exp(-i omega_r (t - t_k))
+      cx<R> xy = cx<R>(w[i][0], w[i][1]) * expi(-(wr * tau_i));
+      w[i][0] = xy.real();
+      w[i][1] = xy.imag();
+      w[i][2] = w[i][2] - wr;
+    }
+    R th1[4], th2[4];
+    for (int j = 0; j < 4; ++j) {
+      th1[j] = (wp * w[0][j] + wm * w[1][j]) * dt;
+      th2[j] = (wm * w[0][j] + wp * w[1][j]) * dt;
+    }
+    Mat<R, N> E1 = Exp<R, N>::apply(th1, p.n_squares);
+    Mat<R, N> E2 = Exp<R, N>::apply(th2, p.n_squares);
+    U = matmul(E2, matmul(E1, U));
+  }
+  // leave the rotating frame: U_k = diag(exp(-i m omega_r Dt)) U_k^r
+  for (int i = 0; i < N; ++i) {
+    cx<R> ph = expi(-(mval<R>(N, i) * (wr * Dt)));
+    for (int j = 0; j < N; ++j) U.m[i][j] = ph * U.m[i][j];
+  }
+  return U;
+}
+
+template <class R, int N>
+void store(const Mat<R, N>& M, R* out) {
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      out[2 * (i * N + j)] = M.m[i][j].real();
+      out[2 * (i * N + j) + 1] = M.m[i][j].imag();
+    }
+}
+
+template <class R, int N>
+Mat<R, N> load(const R* in) {
+  Mat<R, N> M;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) M.m[i][j] = cx<R>(in[2 * (i * N + j)], in[2 * (i * N + j) + 1]);
+  return M;
+}
+
+template <class R, int N>
+void operators(const OProblem& p, const R* params, int64_t k0, int64_t count, R* U) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t c = 0; c < count; ++c) {
+    Mat<R, N> M = interval_operator<R, N>(p, params, k0 + c);
+    store<R, N>(M, U + 2 * N * N * c);
+  }
+}
+
+// psi_0 = psi0, psi_{k+1} = U_k psi_k, psi_final = U_{K-1} psi_{K-1}
+template <class R, int N>
+void states(int64_t K, const R* U, const R* psi0, R* psi, R* psi_final) {
+  cx<R> v[N];
+  for (int i = 0; i < N; ++i) v[i] = cx<R>(psi0[2 * i], psi0[2 * i + 1]);
+  for (int64_t k = 0; k < K; ++k) {
+    if (psi) {
+      for (int i = 0; i < N; ++i) {
+        psi[2 * (N * k + i)] = v[i].real();
+        psi[2 * (N * k + i) + 1] = v[i].imag();
+      }
+    }
+    Mat<R, N> M = load<R, N>(U + 2 * N * N * k);
+    cx<R> w[N];
+    for (int i = 0; i < N; ++i) {
+      cx<R> s(0, 0);
+      for (int j = 0; j < N; ++j) s += M.m[i][j] * v[j];
+      w[i] = s;
+    }
+    for (int i = 0; i < N; ++i) v[i] = w[i];
+  }
+  if (psi_final)
+    for (int i = 0; i < N; ++i) {
+      psi_final[2 * i] = v[i].real();
+      psi_final[2 * i + 1] = v[i].imag();
+    }
+}
+
+template <class R>
+int solve(const OProblem* p, const R* params, const R* psi0, R* U, R* psi, R* psi_final) {
+  if (!p || p->n_samples < 1 || p->n_fine < 1) return 1;
+  const int N = p->spin_twice + 1;
+  if (N != 2 && N != 3) return 1;
+  std::vector<R> tmp;
+  if (!U) {
+    tmp.resize((size_t)p->n_samples * 2 * N * N);
+    U = tmp.data();
+  }
+  if (N == 2) {
+    operators<R, 2>(*p, params, 0, p->n_samples, U);
+    states<R, 2>(p->n_samples, U, psi0, psi, psi_final);
+  } else {
+    operators<R, 3>(*p, params, 0, p->n_samples, U);
+    states<R, 3>(p->n_samples, U, psi0, psi, psi_final);
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }
+
+void oracle_field(const OProblem* p, const double* params, double t, double* out4) {
+  field<double>(*p, params, t, out4);
+}
+
+void oracle_exp_half(const double* th3, double* out8) {
+  store<double, 2>(exp_half<double>(th3), out8);
+}
+
+void oracle_exp_one(const double* th4, int tau, double* out18) {
+  store<double, 3>(exp_one<double>(th4, tau), out18);
+}
+
+void oracle_lie_trotter_residual(const double* th4, int tau, double* out18) {
+  store<double, 3>(lie_trotter_residual<double>(th4, tau), out18);
+}
+
+int oracle_operators(const OProblem* p, const double* params, int64_t k0, int64_t count,
+                     double* U) {
+  if (!p || k0 < 0 || count < 0 || k0 + count > p->n_samples) return 1;
+  if (p->spin_twice == 1) operators<double, 2>(*p, params, k0, count, U);
+  else if (p->spin_twice == 2) operators<double, 3>(*p, params, k0, count, U);
+  else return 1;
+  return 0;
+}
+
+int oracle_states(int spin_twice, int64_t K, const double* U, const double* psi0, double* psi,
+                  double* psi_final) {
+  if (spin_twice == 1) states<double, 2>(K, U, psi0, psi, psi_final);
+  else if (spin_twice == 2) states<double, 3>(K, U, psi0, psi, psi_final);
+  else return 1;
+  return 0;
+}
+
+int oracle_solve(const OProblem* p, const double* params, const double* psi0, double* U,
+                 double* psi, double* psi_final) {
+  return solve<double>(p, params, psi0, U, psi, psi_final);
+}
+
+// Extended-precision instance (x86 80-bit long double), used for finite
+// differences whose step must sit far above the rounding floor.
+int oracle_solve_ld(const OProblem* p, const long double* params, const long double* psi0,
+                    long double* psi_final) {
+  return solve<long double>(p, params, psi0, nullptr, nullptr, psi_final);
+}
+
+}  // extern "C"
