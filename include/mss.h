@@ -1,0 +1,175 @@
+/* mss.h -- C ABI of the MI355X (gfx950) spin-1/2 / spin-1 Schroedinger solver.
+ *
+ * Method: arXiv:2204.05586 ("Spinsim").  The library integrates
+ *   i d psi / dt = H(t) psi,   H(t) = 2 pi (f_x J_x + f_y J_y + f_z J_z [+ f_q Q])
+ * (Sec. "Quantum mechanics background"; hbar = 1, fields f_j in Hz,
+ * J = sigma/2 for spin-1/2, the spin-1 matrices and Q = diag(1,-2,1)/3 for
+ * spin-1, basis ordered m = +s ... -s).  For every output interval
+ * [t_k, t_k + Dt] it builds the time-evolution operator U_k from L fine
+ * commutator-free fourth-order Magnus (CF4) steps (Sec. "Unitary time
+ * evolution and the Magnus expansion", eqs. cf4_sample_1/2 and
+ * cf4_implementation) inside a per-interval rotating frame (Sec.
+ * "Dynamically rotating frame", eq. exit_rotating_frame), with an analytic
+ * SU(2) exponential for spin-1/2 and the Lie-Trotter exponentiator with
+ * 2^tau residual squarings for spin-1 (Sec. "Lie-Trotter based
+ * exponentiator", eq. lie_trotter_4).  The state series is the ordered
+ * product psi_0 = psi_init, psi_{k+1} = U_k psi_k (Sec. "Discretization and
+ * parallelization", eq. integration_compilation), computed on the GPU as
+ * an associative prefix product.
+ *
+ * Conventions
+ *   complex   interleaved double (re, im); matrices row-major; N = 2 or 3
+ *   U         [K][N][N] complex  (K*N*N*2 doubles)
+ *   psi       [K][N] complex     psi[k] = psi(t_k), psi[0] = psi_init
+ *   psi_final [N] complex        psi(t_start + K Dt)
+ *   time      [K] double         t_k = t_start + k * Dt
+ *   units     seconds and Hz
+ *
+ * Ownership: the caller owns every buffer.  Array arguments of the solve
+ * calls are DEVICE pointers (HIP device memory of the current device);
+ * mss_problem and its term array are HOST memory and are only read during
+ * the call.  `stream` is a hipStream_t (NULL: the default stream); work is
+ * enqueued asynchronously and the library keeps no pointer after return.
+ *
+ * Errors: every call returns an mss_status.  Arguments are validated on
+ * the host before anything is launched; on failure nothing is launched and
+ * mss_last_error() (thread-local) describes the problem.  A HIP runtime
+ * failure returns MSS_E_DEVICE with the HIP error string.
+ */
+#ifndef MSS_H
+#define MSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSS_MAX_TERMS 32
+#define MSS_MAX_SQUARES 60
+
+typedef enum mss_status {
+  MSS_OK = 0,
+  MSS_E_INVALID = 1,     /* bad argument (see mss_last_error) */
+  MSS_E_NOMEM = 2,       /* workspace too small or device memory exhausted */
+  MSS_E_DEVICE = 3,      /* HIP runtime failure / no usable device */
+  MSS_E_UNSUPPORTED = 4, /* valid request this build cannot run */
+  MSS_E_BUSY = 5,
+  MSS_E_NOTREADY = 6
+} mss_status;
+
+/* Field-program term kinds.  A term adds to component `comp` at time t,
+ * only while t_on < t < t_off (use -inf / +inf for "always"):
+ *   MSS_TERM_CONST    a
+ *   MSS_TERM_COS      a * cos(2 pi f t + phi)
+ *   MSS_TERM_SIN      a * sin(2 pi f t + phi)
+ *   MSS_TERM_PWC      a_s
+ *   MSS_TERM_PWC_COS  a_s * cos(2 pi f t + phi_s)
+ *   MSS_TERM_PWC_SIN  a_s * sin(2 pi f t + phi_s)
+ * with s = clamp(floor((t - seg_t0) / seg_len), 0, n_seg - 1),
+ * a_s = params[seg_a_slot + s] (literal a if seg_a_slot < 0) and
+ * phi_s = params[seg_phi_slot + s] (literal phi if seg_phi_slot < 0).
+ * a, f, phi are replaced by params[a_slot], params[f_slot], params[phi_slot]
+ * when the slot is >= 0 -- the per-simulation parameter vector plays the
+ * role of the paper's sweep_parameters (Sec. "Compilation of integrator").
+ * The phase is evaluated as 2 pi * (f * t) + phi; terms of one component
+ * are summed in list order. */
+typedef enum mss_term_kind {
+  MSS_TERM_CONST = 0,
+  MSS_TERM_COS = 1,
+  MSS_TERM_SIN = 2,
+  MSS_TERM_PWC = 3,
+  MSS_TERM_PWC_COS = 4,
+  MSS_TERM_PWC_SIN = 5
+} mss_term_kind;
+
+typedef enum mss_component { MSS_X = 0, MSS_Y = 1, MSS_Z = 2, MSS_Q = 3 } mss_component;
+
+typedef struct mss_term {
+  int32_t kind;          /* mss_term_kind */
+  int32_t comp;          /* mss_component; MSS_Q only for spin-1 */
+  int32_t a_slot, f_slot, phi_slot;     /* -1: literal */
+  int32_t n_seg;         /* PWC kinds: number of segments (>= 1) */
+  int32_t seg_a_slot, seg_phi_slot;     /* first slot of the per-segment arrays, -1: literal */
+  double a, f, phi;      /* Hz, Hz, rad */
+  double t_on, t_off;    /* s */
+  double seg_t0, seg_len;/* s; seg_len > 0 for PWC kinds */
+} mss_term;
+
+typedef struct mss_problem {
+  int32_t spin_twice;     /* 1: spin-1/2 (N = 2), 2: spin-1 (N = 3) */
+  int32_t n_terms;        /* 0 .. MSS_MAX_TERMS */
+  const mss_term* terms;  /* host array of n_terms terms */
+  int32_t n_params;       /* length of the parameter vector (>= every slot used + 1) */
+  int32_t n_fine;         /* L >= 1 fine CF4 steps per interval, dt = Dt / L */
+  int64_t n_samples;      /* K >= 1 output intervals */
+  double t_start;         /* s, finite */
+  double dt_out;          /* Dt > 0, s */
+  int32_t n_squares;      /* tau in [0, MSS_MAX_SQUARES], spin-1 only (paper default 24) */
+  int32_t rotating_frame; /* 0/1: per-interval frame at omega_r = 2 pi f_z(t_k + Dt/2) */
+} mss_problem;
+
+/* Launch shape of the integrator.  slices: lanes cooperating on one
+ * interval (power of two, 1..64, <= n_fine); each lane takes a contiguous
+ * run of fine steps and the partial products are combined in order.
+ * block: threads per workgroup (64, 128, 256, 512 or 1024).
+ * Zero fields mean "choose" (mss_plan_launch). */
+typedef struct mss_launch {
+  int32_t slices;
+  int32_t block;
+} mss_launch;
+
+/* Human-readable name of a status code (static string). */
+const char* mss_status_str(mss_status s);
+
+/* Last error message of the calling thread ("" if none). */
+const char* mss_last_error(void);
+
+/* Library version string, e.g. "mss 0.1 gfx950". */
+const char* mss_version(void);
+
+/* Host-only validation of a problem (Sec. "Discretization and
+ * parallelization": K, L, Dt; field program limits).  No device access. */
+mss_status mss_validate(const mss_problem* p);
+
+/* Launch shape the library would use for `p` on the current device (or a
+ * 256-CU gfx950 when no device is visible).  Host only. */
+mss_status mss_plan_launch(const mss_problem* p, mss_launch* out);
+
+/* Bytes of device workspace mss_solve needs for `p`; store_u = 0 means
+ * the caller passes U = NULL, so the operators live in the workspace.
+ * Host only. */
+mss_status mss_workspace_size(const mss_problem* p, int32_t store_u, size_t* bytes);
+
+/* Bytes of device workspace mss_propagate needs for K operators of size N. */
+mss_status mss_propagate_workspace_size(int32_t spin_twice, int64_t n_samples, size_t* bytes);
+
+/* Interval operators U_k, k = 0..K-1 (the integrator: CF4 fine steps in the
+ * rotating frame, then the frame exit).  params: device array of
+ * p->n_params doubles (may be NULL when n_params == 0).  U: device output
+ * [K][N][N] complex.  time: optional device output [K] (NULL: skipped).
+ * launch: NULL for the planned shape. */
+mss_status mss_integrate(const mss_problem* p, const double* params, double* U, double* time,
+                         const mss_launch* launch, void* stream);
+
+/* Ordered product of operators (eq. integration_compilation):
+ * psi[0] = psi0, psi[k+1] = U[k] psi[k], psi_final = U[K-1] psi[K-1].
+ * U: device [K][N][N]; psi0: device [N]; psi: device [K][N] (required);
+ * psi_final: device [N] or NULL.  ws: device workspace of at least
+ * mss_propagate_workspace_size bytes (may be NULL if that size is 0). */
+mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
+                         const double* psi0, double* psi, double* psi_final, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Whole path: mss_integrate then mss_propagate.  U may be NULL (the
+ * operators then live in the workspace, see mss_workspace_size). */
+mss_status mss_solve(const mss_problem* p, const double* params, const double* psi0, double* U,
+                     double* psi, double* psi_final, double* time, void* ws, size_t ws_bytes,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSS_H */

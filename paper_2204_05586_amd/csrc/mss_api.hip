@@ -1,0 +1,327 @@
+// C ABI of the solver (include/mss.h): host-side validation, launch
+// planning, workspace layout and the launch sequence of the path.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "mss_internal.h"
+
+using namespace mss;
+
+namespace {
+
+thread_local std::string g_err;
+
+mss_status fail(mss_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+mss_status ok() {
+  g_err.clear();
+  return MSS_OK;
+}
+
+mss_status hip_fail(hipError_t e, const char* what) {
+  return fail(MSS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool finite(double x) { return isfinite(x) != 0; }
+
+bool slot_ok(int32_t slot, int32_t count, int32_t n_params) {
+  return slot < 0 || ((int64_t)slot + count <= (int64_t)n_params);
+}
+
+// Compute units of the current device (256 on an MI355X; also the value
+// assumed when no device is visible, so planning works host-only).
+int device_cu_count() {
+  static std::mutex mu;
+  static int cache[64];
+  static bool init = false;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!init) {
+    for (int& c : cache) c = -1;
+    init = true;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  if (cache[dev] < 0) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cu <= 0) {
+      (void)hipGetLastError();
+      cu = 256;
+    }
+    cache[dev] = cu;
+  }
+  return cache[dev];
+}
+
+int ilog2(int x) {
+  int l = 0;
+  while ((1 << (l + 1)) <= x) ++l;
+  return l;
+}
+
+// Lane-slice count: minimise (waves per SIMD, rounded up) x (fine steps per
+// lane, rounded up); ties go to fewer slices.
+int plan_slices(int64_t K, int32_t L, int cu) {
+  const int64_t simds = (int64_t)cu * 4;
+  int best = 1;
+  double best_cost = 1e300;
+  for (int S = 1; S <= 64 && S <= L; S <<= 1) {
+    const int64_t waves = (K * S + 63) / 64;
+    const int64_t per_simd = (waves + simds - 1) / simds;
+    const int64_t steps = (L + S - 1) / S;
+    const double cost = (double)per_simd * ((double)steps + 0.1 * ilog2(S));
+    if (cost < best_cost * (1.0 - 1e-9)) {
+      best_cost = cost;
+      best = S;
+    }
+  }
+  return best;
+}
+
+struct ScanLevels {
+  int n_levels;         // number of levels above the operators (0: single tile)
+  int64_t n[8];         // n[0] = K, n[l] = elements at level l
+  size_t agg_off[8];    // workspace offsets of level-l aggregates (l >= 1)
+  size_t state_off[8];  // workspace offsets of level-l entering states (l >= 1)
+  size_t bytes;
+};
+
+ScanLevels plan_scan(int N, int64_t K) {
+  ScanLevels s{};
+  s.n[0] = K;
+  size_t off = 0;
+  int l = 0;
+  while (s.n[l] > kScanTile) {
+    s.n[l + 1] = (s.n[l] + kScanTile - 1) / kScanTile;
+    ++l;
+    s.agg_off[l] = off;
+    off += align256((size_t)s.n[l] * 2 * N * N * sizeof(double));
+    s.state_off[l] = off;
+    off += align256((size_t)s.n[l] * 2 * N * sizeof(double));
+  }
+  s.n_levels = l;
+  s.bytes = off;
+  return s;
+}
+
+mss_status validate_problem(const mss_problem* p) {
+  if (!p) return fail(MSS_E_INVALID, "problem is NULL");
+  if (p->spin_twice != 1 && p->spin_twice != 2)
+    return fail(MSS_E_INVALID, "spin_twice must be 1 (spin-1/2) or 2 (spin-1), got %d",
+                p->spin_twice);
+  if (p->n_terms < 0 || p->n_terms > MSS_MAX_TERMS)
+    return fail(MSS_E_INVALID, "n_terms must be in [0, %d], got %d", MSS_MAX_TERMS, p->n_terms);
+  if (p->n_terms > 0 && !p->terms) return fail(MSS_E_INVALID, "terms is NULL");
+  if (p->n_params < 0) return fail(MSS_E_INVALID, "n_params must be >= 0");
+  if (p->n_fine < 1) return fail(MSS_E_INVALID, "n_fine (L) must be >= 1, got %d", p->n_fine);
+  if (p->n_samples < 1)
+    return fail(MSS_E_INVALID, "n_samples (K) must be >= 1, got %lld", (long long)p->n_samples);
+  if (p->n_samples > ((int64_t)1 << 40))
+    return fail(MSS_E_INVALID, "n_samples (K) too large: %lld", (long long)p->n_samples);
+  if (!finite(p->t_start)) return fail(MSS_E_INVALID, "t_start is not finite");
+  if (!finite(p->dt_out) || !(p->dt_out > 0.0))
+    return fail(MSS_E_INVALID, "dt_out must be finite and > 0");
+  if (!finite(p->t_start + (double)p->n_samples * p->dt_out))
+    return fail(MSS_E_INVALID, "t_start + K * dt_out is not finite");
+  if (p->n_squares < 0 || p->n_squares > MSS_MAX_SQUARES)
+    return fail(MSS_E_INVALID, "n_squares (tau) must be in [0, %d], got %d", MSS_MAX_SQUARES,
+                p->n_squares);
+  if (p->rotating_frame != 0 && p->rotating_frame != 1)
+    return fail(MSS_E_INVALID, "rotating_frame must be 0 or 1");
+  for (int i = 0; i < p->n_terms; ++i) {
+    const mss_term& t = p->terms[i];
+    if (t.kind < MSS_TERM_CONST || t.kind > MSS_TERM_PWC_SIN)
+      return fail(MSS_E_INVALID, "term %d: unknown kind %d", i, t.kind);
+    if (t.comp < 0 || t.comp > 3) return fail(MSS_E_INVALID, "term %d: comp must be 0..3", i);
+    if (t.comp == MSS_Q && p->spin_twice != 2)
+      return fail(MSS_E_INVALID, "term %d: the quadrupole component needs spin-1", i);
+    if (!finite(t.a) || !finite(t.f) || !finite(t.phi))
+      return fail(MSS_E_INVALID, "term %d: a, f, phi must be finite", i);
+    if (isnan(t.t_on) || isnan(t.t_off)) return fail(MSS_E_INVALID, "term %d: NaN window", i);
+    if (!slot_ok(t.a_slot, 1, p->n_params) || !slot_ok(t.f_slot, 1, p->n_params) ||
+        !slot_ok(t.phi_slot, 1, p->n_params))
+      return fail(MSS_E_INVALID, "term %d: parameter slot beyond n_params = %d", i, p->n_params);
+    if (t.kind >= MSS_TERM_PWC) {
+      if (t.n_seg < 1) return fail(MSS_E_INVALID, "term %d: n_seg must be >= 1", i);
+      if (!finite(t.seg_t0) || !finite(t.seg_len) || !(t.seg_len > 0.0))
+        return fail(MSS_E_INVALID, "term %d: seg_t0 finite and seg_len > 0 required", i);
+      if (!slot_ok(t.seg_a_slot, t.n_seg, p->n_params) ||
+          !slot_ok(t.seg_phi_slot, t.n_seg, p->n_params))
+        return fail(MSS_E_INVALID, "term %d: segment slots beyond n_params = %d", i, p->n_params);
+    }
+  }
+  return MSS_OK;
+}
+
+mss_status resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block) {
+  int S = in ? in->slices : 0;
+  int B = in ? in->block : 0;
+  if (S == 0) S = plan_slices(p->n_samples, p->n_fine, device_cu_count());
+  if (B == 0) B = 256;
+  if (S < 1 || S > 64 || (S & (S - 1)) != 0 || S > p->n_fine)
+    return fail(MSS_E_INVALID, "launch.slices must be a power of two in [1, min(64, L)], got %d",
+                S);
+  if (B != 64 && B != 128 && B != 256)
+    return fail(MSS_E_INVALID, "launch.block must be 64, 128 or 256, got %d", B);
+  const int64_t grid = (p->n_samples * S + B - 1) / B;
+  if (grid > 0x7fffffffLL) return fail(MSS_E_INVALID, "grid too large");
+  *slices = S;
+  *block = B;
+  return MSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mss_status_str(mss_status s) {
+  switch (s) {
+    case MSS_OK: return "MSS_OK";
+    case MSS_E_INVALID: return "MSS_E_INVALID";
+    case MSS_E_NOMEM: return "MSS_E_NOMEM";
+    case MSS_E_DEVICE: return "MSS_E_DEVICE";
+    case MSS_E_UNSUPPORTED: return "MSS_E_UNSUPPORTED";
+    case MSS_E_BUSY: return "MSS_E_BUSY";
+    case MSS_E_NOTREADY: return "MSS_E_NOTREADY";
+  }
+  return "MSS_E_UNKNOWN";
+}
+
+const char* mss_last_error(void) { return g_err.c_str(); }
+
+const char* mss_version(void) { return "mss 0.1 gfx950"; }
+
+mss_status mss_validate(const mss_problem* p) {
+  mss_status s = validate_problem(p);
+  return s == MSS_OK ? ok() : s;
+}
+
+mss_status mss_plan_launch(const mss_problem* p, mss_launch* out) {
+  mss_status s = validate_problem(p);
+  if (s != MSS_OK) return s;
+  if (!out) return fail(MSS_E_INVALID, "out is NULL");
+  int S, B;
+  if ((s = resolve_launch(p, nullptr, &S, &B)) != MSS_OK) return s;
+  out->slices = S;
+  out->block = B;
+  return ok();
+}
+
+mss_status mss_propagate_workspace_size(int32_t spin_twice, int64_t n_samples, size_t* bytes) {
+  if (spin_twice != 1 && spin_twice != 2) return fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
+  if (n_samples < 1) return fail(MSS_E_INVALID, "n_samples must be >= 1");
+  if (!bytes) return fail(MSS_E_INVALID, "bytes is NULL");
+  *bytes = plan_scan(spin_twice + 1, n_samples).bytes;
+  return ok();
+}
+
+mss_status mss_workspace_size(const mss_problem* p, int32_t store_u, size_t* bytes) {
+  mss_status s = validate_problem(p);
+  if (s != MSS_OK) return s;
+  if (!bytes) return fail(MSS_E_INVALID, "bytes is NULL");
+  const int N = p->spin_twice + 1;
+  size_t b = plan_scan(N, p->n_samples).bytes;
+  if (!store_u) b += align256((size_t)p->n_samples * 2 * N * N * sizeof(double));
+  *bytes = b;
+  return ok();
+}
+
+mss_status mss_integrate(const mss_problem* p, const double* params, double* U, double* time,
+                         const mss_launch* launch, void* stream) {
+  mss_status s = validate_problem(p);
+  if (s != MSS_OK) return s;
+  if (!U) return fail(MSS_E_INVALID, "U is NULL");
+  if (p->n_params > 0 && !params) return fail(MSS_E_INVALID, "params is NULL but n_params > 0");
+  int S, B;
+  if ((s = resolve_launch(p, launch, &S, &B)) != MSS_OK) return s;
+  IntegrateArgs a;
+  memset(&a, 0, sizeof a);
+  a.fp.n_terms = p->n_terms;
+  for (int i = 0; i < p->n_terms; ++i) a.fp.t[i] = p->terms[i];
+  a.params = params;
+  a.U = U;
+  a.time = time;
+  a.t_start = p->t_start;
+  a.dt_out = p->dt_out;
+  a.dt = p->dt_out / (double)p->n_fine;
+  a.K = p->n_samples;
+  a.L = p->n_fine;
+  a.tau = p->spin_twice == 2 ? p->n_squares : 0;
+  a.frame = p->rotating_frame;
+  a.slices_log2 = ilog2(S);
+  hipError_t e = launch_integrate(p->spin_twice + 1, a, B, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "integrate launch");
+  return ok();
+}
+
+mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
+                         const double* psi0, double* psi, double* psi_final, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (spin_twice != 1 && spin_twice != 2) return fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
+  if (n_samples < 1) return fail(MSS_E_INVALID, "n_samples must be >= 1");
+  if (!U || !psi0 || !psi) return fail(MSS_E_INVALID, "U, psi0 and psi are required");
+  const int N = spin_twice + 1;
+  const ScanLevels lv = plan_scan(N, n_samples);
+  if (lv.bytes > 0 && (!ws || ws_bytes < lv.bytes))
+    return fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", lv.bytes,
+                ws ? ws_bytes : (size_t)0);
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const double* M[8];
+  M[0] = U;
+  for (int l = 1; l <= lv.n_levels; ++l) M[l] = (const double*)(w + lv.agg_off[l]);
+  hipError_t e;
+  for (int l = 0; l < lv.n_levels; ++l) {
+    e = launch_scan_reduce(N, M[l], lv.n[l], (double*)M[l + 1], st);
+    if (e != hipSuccess) return hip_fail(e, "scan reduce launch");
+  }
+  // top level: one tile entered with psi0
+  for (int l = lv.n_levels; l >= 0; --l) {
+    const double* start = (l == lv.n_levels) ? psi0 : (const double*)(w + lv.state_off[l + 1]);
+    double* before = (l == 0) ? psi : (double*)(w + lv.state_off[l]);
+    double* after = (l == 0) ? psi_final : nullptr;
+    e = launch_scan_apply(N, M[l], lv.n[l], start, before, after, st);
+    if (e != hipSuccess) return hip_fail(e, "scan apply launch");
+  }
+  return ok();
+}
+
+mss_status mss_solve(const mss_problem* p, const double* params, const double* psi0, double* U,
+                     double* psi, double* psi_final, double* time, void* ws, size_t ws_bytes,
+                     void* stream) {
+  mss_status s = validate_problem(p);
+  if (s != MSS_OK) return s;
+  if (!psi0 || !psi) return fail(MSS_E_INVALID, "psi0 and psi are required");
+  const int N = p->spin_twice + 1;
+  size_t need = 0;
+  if ((s = mss_workspace_size(p, U != nullptr, &need)) != MSS_OK) return s;
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", need,
+                ws ? ws_bytes : (size_t)0);
+  char* w = (char*)ws;
+  const size_t scan_bytes = plan_scan(N, p->n_samples).bytes;
+  double* Uw = U ? U : (double*)(w + scan_bytes);
+  if ((s = mss_integrate(p, params, Uw, time, nullptr, stream)) != MSS_OK) return s;
+  return mss_propagate(p->spin_twice, p->n_samples, Uw, psi0, psi, psi_final, ws, scan_bytes,
+                       stream);
+}
+
+}  // extern "C"

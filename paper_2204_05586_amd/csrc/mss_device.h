@@ -1,0 +1,371 @@
+// Device-side building blocks of the solver: small complex matrices held in
+// registers, the two exponentiators, the field-program interpreter and one
+// CF4 fine step.  gfx950 only: FP64 on the vector ALUs (a 3x3 complex
+// product is 108 FP64 FMAs and not a dense contraction worth MFMA).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mss.h"
+
+namespace mss {
+
+// ---------------------------------------------------------------------------
+// constants (IEEE double values of the printed closed forms)
+// ---------------------------------------------------------------------------
+// Gauss-Legendre nodes (1 -/+ 1/sqrt 3) / 2 and CF4 weights (3 +/- 2 sqrt 3) / 12
+// (Sec. "Unitary time evolution and the Magnus expansion", eqs. cf4_sample_1/2).
+constexpr double kNode1 = 0x1.b0cb174df99c6p-3;
+constexpr double kNode2 = 0x1.93cd3a2c8198ep-1;
+constexpr double kWPlus = 0x1.13cd3a2c8198ep-1;
+constexpr double kWMinus = -0x1.3cd3a2c8198e0p-5;
+constexpr double kTwoPi = 0x1.921fb54442d18p+2;
+constexpr double kRsqrt2 = 0x1.6a09e667f3bccp-1;
+
+// Field program as a kernel argument (scalar-loaded, uniform across a wave).
+struct FieldProgram {
+  int32_t n_terms;
+  int32_t pad;
+  mss_term t[MSS_MAX_TERMS];
+};
+
+template <int N>
+struct Mat {
+  double r[N][N];
+  double i[N][N];
+};
+
+template <int N>
+__device__ __forceinline__ void set_identity(Mat<N>& m) {
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      m.r[a][b] = (a == b) ? 1.0 : 0.0;
+      m.i[a][b] = 0.0;
+    }
+}
+
+// C = A * B (complex, N x N), 4 real FMAs per complex multiply-add.
+template <int N>
+__device__ __forceinline__ void matmul(const Mat<N>& A, const Mat<N>& B, Mat<N>& C) {
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      double re = A.r[a][0] * B.r[0][b];
+      double im = A.r[a][0] * B.i[0][b];
+      re = fma(-A.i[a][0], B.i[0][b], re);
+      im = fma(A.i[a][0], B.r[0][b], im);
+#pragma unroll
+      for (int k = 1; k < N; ++k) {
+        re = fma(A.r[a][k], B.r[k][b], re);
+        re = fma(-A.i[a][k], B.i[k][b], re);
+        im = fma(A.r[a][k], B.i[k][b], im);
+        im = fma(A.i[a][k], B.r[k][b], im);
+      }
+      C.r[a][b] = re;
+      C.i[a][b] = im;
+    }
+}
+
+// M <- A * M
+template <int N>
+__device__ __forceinline__ void premultiply(const Mat<N>& A, Mat<N>& M) {
+  Mat<N> t;
+  matmul<N>(A, M, t);
+  M = t;
+}
+
+template <int N>
+__device__ __forceinline__ Mat<N> shfl_down_mat(const Mat<N>& m, int d) {
+  Mat<N> o;
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      o.r[a][b] = __shfl_down(m.r[a][b], d, 64);
+      o.i[a][b] = __shfl_down(m.i[a][b], d, 64);
+    }
+  return o;
+}
+
+template <int N>
+__device__ __forceinline__ Mat<N> shfl_up_mat(const Mat<N>& m, int d) {
+  Mat<N> o;
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      o.r[a][b] = __shfl_up(m.r[a][b], d, 64);
+      o.i[a][b] = __shfl_up(m.i[a][b], d, 64);
+    }
+  return o;
+}
+
+template <int N>
+__device__ __forceinline__ void load_mat(const double* __restrict__ p, Mat<N>& m) {
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      m.r[a][b] = p[2 * (a * N + b)];
+      m.i[a][b] = p[2 * (a * N + b) + 1];
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void store_mat(double* __restrict__ p, const Mat<N>& m) {
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      p[2 * (a * N + b)] = m.r[a][b];
+      p[2 * (a * N + b) + 1] = m.i[a][b];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sine / cosine of the tiny angles inside the exponentiators
+// ---------------------------------------------------------------------------
+// Below 2^-10 the Taylor series to x^5 (sin) and x^6 (cos) is exact to
+// far below one ulp (next terms < 2e-22 relative); above it, ocml's sincos.
+__device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
+  if (fabs(x) < 0x1p-10) {
+    const double x2 = x * x;
+    *s = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
+    *c = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  } else {
+    sincos(x, s, c);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// spin-1/2 exponential: exp(-i theta . sigma / 2)
+// = cos(|theta|/2) I - i sin(|theta|/2) (theta/|theta|) . sigma
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void exp_half(const double th[4], int /*tau*/, Mat<2>& E) {
+  const double t2 = fma(th[0], th[0], fma(th[1], th[1], th[2] * th[2]));
+  const double big = sqrt(t2);
+  const double x = 0.5 * big;
+  double c, S;  // S = sin(|theta|/2) / |theta|
+  if (x < 0x1p-10) {
+    const double x2 = x * x;
+    c = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    S = 0.5 * fma(x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), 1.0);
+  } else {
+    double s;
+    sincos(x, &s, &c);
+    S = s / big;
+  }
+  E.r[0][0] = c;           E.i[0][0] = -S * th[2];
+  E.r[0][1] = -S * th[1];  E.i[0][1] = -S * th[0];
+  E.r[1][0] = S * th[1];   E.i[1][0] = -S * th[0];
+  E.r[1][1] = c;           E.i[1][1] = S * th[2];
+}
+
+// ---------------------------------------------------------------------------
+// spin-1 Lie-Trotter exponential (Sec. "Lie-Trotter based exponentiator")
+// ---------------------------------------------------------------------------
+// Residual a = T - I of T = exp(-iD/2) exp(-i Phi J_phi) exp(-iD/2) with
+// z = theta_z / n, q = theta_q / n, Phi = |theta_xy| / n, n = 2^tau,
+// written entry by entry (element-wise form of the paper with the T_13 and
+// T_22 misprints corrected); diagonals as (e^{i b} - 1) - k S^2 e^{i b} with
+// e^{i b} - 1 = -2 sin^2(b/2) + i sin b, so nothing cancels.
+__device__ __forceinline__ void lie_trotter_residual(const double th[4], int tau, Mat<3>& a) {
+  const double ninv = ldexp(1.0, -tau);
+  const double z = th[2] * ninv;
+  const double q = th[3] * ninv;
+  const double rho = hypot(th[0], th[1]);
+  const double Phi = rho * ninv;
+  double epr = 1.0, epi = 0.0;  // e^{i phi} = (theta_x + i theta_y) / rho
+  if (rho > 0.0) {
+    const double inv = 1.0 / rho;
+    epr = th[0] * inv;
+    epi = th[1] * inv;
+  }
+  double S, C;
+  sincos_small(0.5 * Phi, &S, &C);
+  const double S2 = S * S;
+  const double rs = kRsqrt2 * (2.0 * S * C);  // sin(Phi) / sqrt 2
+  double sz, cz, sq, cq;
+  sincos_small(0.5 * z, &sz, &cz);           // e^{i z/2}
+  sincos_small(q * (1.0 / 6.0), &sq, &cq);   // e^{i q/6}
+  // g = e^{iq/6} e^{-iz/2}, h = e^{iq/6} e^{iz/2}
+  const double gr = fma(cq, cz, sq * sz), gi = fma(sq, cz, -cq * sz);
+  const double hr = fma(cq, cz, -sq * sz), hi = fma(sq, cz, cq * sz);
+  // x * e^{-/+ i phi}
+  const double gmr = fma(gr, epr, gi * epi), gmi = fma(gi, epr, -gr * epi);
+  const double gpr = fma(gr, epr, -gi * epi), gpi = fma(gi, epr, gr * epi);
+  const double hmr = fma(hr, epr, hi * epi), hmi = fma(hi, epr, -hr * epi);
+  const double hpr = fma(hr, epr, -hi * epi), hpi = fma(hi, epr, hr * epi);
+  // (-i rs) (x + i y) = rs y - i rs x
+  a.r[0][1] = rs * gmi;  a.i[0][1] = -rs * gmr;
+  a.r[1][0] = rs * gpi;  a.i[1][0] = -rs * gpr;
+  a.r[1][2] = rs * hmi;  a.i[1][2] = -rs * hmr;
+  a.r[2][1] = rs * hpi;  a.i[2][1] = -rs * hpr;
+  // T_13 = -S^2 e^{-iq/3} e^{-2i phi}, T_31 = -S^2 e^{-iq/3} e^{2i phi}
+  const double e3r = fma(cq, cq, -sq * sq), e3i = -2.0 * sq * cq;  // e^{-iq/3}
+  const double e2r = fma(epr, epr, -epi * epi), e2i = 2.0 * epr * epi;  // e^{2i phi}
+  a.r[0][2] = -S2 * fma(e3r, e2r, e3i * e2i);
+  a.i[0][2] = -S2 * fma(e3i, e2r, -e3r * e2i);
+  a.r[2][0] = -S2 * fma(e3r, e2r, -e3i * e2i);
+  a.i[2][0] = -S2 * fma(e3i, e2r, e3r * e2i);
+  // diagonals, b1 = -z - q/3, b2 = 2q/3, b3 = z - q/3
+  const double q3 = q * (1.0 / 3.0);
+  const double b[3] = {-z - q3, 2.0 * q3, z - q3};
+  const double k[3] = {S2, 2.0 * S2, S2};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    double sh, ch;
+    sincos_small(0.5 * b[j], &sh, &ch);
+    const double mr = -2.0 * sh * sh;  // Re(e^{ib} - 1)
+    const double mi = 2.0 * sh * ch;   // Im = sin b
+    a.r[j][j] = fma(-k[j], 1.0 + mr, mr);
+    a.i[j][j] = fma(-k[j], mi, mi);
+  }
+}
+
+// tau residual squarings a <- (a + 2I) a, then I + a.
+__device__ __forceinline__ void exp_one(const double th[4], int tau, Mat<3>& E) {
+  Mat<3> a;
+  lie_trotter_residual(th, tau, a);
+  for (int s = 0; s < tau; ++s) {
+    Mat<3> b = a;
+    b.r[0][0] += 2.0;
+    b.r[1][1] += 2.0;
+    b.r[2][2] += 2.0;
+    matmul<3>(b, a, E);
+    a = E;
+  }
+  E = a;
+  E.r[0][0] += 1.0;
+  E.r[1][1] += 1.0;
+  E.r[2][2] += 1.0;
+}
+
+template <int N> struct Exponentiator;
+template <> struct Exponentiator<2> {
+  static __device__ __forceinline__ void apply(const double th[4], int tau, Mat<2>& E) {
+    exp_half(th, tau, E);
+  }
+};
+template <> struct Exponentiator<3> {
+  static __device__ __forceinline__ void apply(const double th[4], int tau, Mat<3>& E) {
+    exp_one(th, tau, E);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// field program interpreter and node arithmetic.  Multiply-adds are kept
+// unfused here, so node times and phase arguments (up to ~1e6 rad) round
+// exactly as the plain definition t_k = t_start + k Dt,
+// tau_i = (l + c_i) dt, phase = 2 pi (f t) + phi prescribes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void field_eval(const FieldProgram& fp, const double* __restrict__ params,
+                                           double t, double f[4]) {
+#pragma clang fp contract(off)
+  double fx = 0.0, fy = 0.0, fz = 0.0, fq = 0.0;
+  for (int n = 0; n < fp.n_terms; ++n) {
+    const mss_term& tm = fp.t[n];
+    if (!(tm.t_on < t && t < tm.t_off)) continue;
+    double amp = tm.a_slot >= 0 ? params[tm.a_slot] : tm.a;
+    const double fr = tm.f_slot >= 0 ? params[tm.f_slot] : tm.f;
+    double ph = tm.phi_slot >= 0 ? params[tm.phi_slot] : tm.phi;
+    const int kind = tm.kind;
+    if (kind >= MSS_TERM_PWC) {
+      const double x = (t - tm.seg_t0) / tm.seg_len;
+      const double fl = floor(x);
+      int s = fl < 0.0 ? 0 : (fl > (double)(tm.n_seg - 1) ? tm.n_seg - 1 : (int)fl);
+      if (tm.seg_a_slot >= 0) amp = params[tm.seg_a_slot + s];
+      if (tm.seg_phi_slot >= 0) ph = params[tm.seg_phi_slot + s];
+    }
+    double v;
+    if (kind == MSS_TERM_CONST || kind == MSS_TERM_PWC) {
+      v = amp;
+    } else {
+      const double ft = fr * t;
+      const double x = kTwoPi * ft;
+      const double arg = x + ph;
+      v = amp * ((kind == MSS_TERM_COS || kind == MSS_TERM_PWC_COS) ? cos(arg) : sin(arg));
+    }
+    switch (tm.comp) {
+      case 0: fx = fx + v; break;
+      case 1: fy = fy + v; break;
+      case 2: fz = fz + v; break;
+      default: fq = fq + v; break;
+    }
+  }
+  f[0] = fx; f[1] = fy; f[2] = fz; f[3] = fq;
+}
+
+// Angles theta_{1,2} = omega_bar_{1,2} dt of one CF4 fine step starting at
+// t_k + l dt, in the frame rotating at wr about z (wr = 0: lab frame).
+__device__ __forceinline__ void cf4_angles(const FieldProgram& fp, const double* __restrict__ params,
+                                           double tk, int l, double dt, double wr,
+                                           double th1[4], double th2[4]) {
+#pragma clang fp contract(off)
+  double w[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double tau_i = ((double)l + (i == 0 ? kNode1 : kNode2)) * dt;
+    double f[4];
+    field_eval(fp, params, tk + tau_i, f);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[i][j] = kTwoPi * f[j];
+    if (wr != 0.0) {
+      // (w_x + i w_y) e^{-i wr tau_i}
+      double s, c;
+      sincos(wr * tau_i, &s, &c);
+      const double xr = w[i][0] * c + w[i][1] * s;
+      const double xi = w[i][1] * c - w[i][0] * s;
+      w[i][0] = xr;
+      w[i][1] = xi;
+      w[i][2] = w[i][2] - wr;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    th1[j] = (kWPlus * w[0][j] + kWMinus * w[1][j]) * dt;
+    th2[j] = (kWMinus * w[0][j] + kWPlus * w[1][j]) * dt;
+  }
+}
+
+// Start time of interval k and the frame rate omega_r = 2 pi f_z(t_k + Dt/2).
+__device__ __forceinline__ void interval_setup(const FieldProgram& fp, const double* __restrict__ params,
+                                               double t_start, double Dt, int64_t k, int frame,
+                                               double* tk_out, double* wr_out) {
+#pragma clang fp contract(off)
+  const double tk = t_start + (double)k * Dt;
+  double wr = 0.0;
+  if (frame) {
+    double f[4];
+    field_eval(fp, params, tk + Dt / 2.0, f);
+    wr = kTwoPi * f[2];
+  }
+  *tk_out = tk;
+  *wr_out = wr;
+}
+
+// U <- diag(exp(-i m wr Dt)) U, m = +s ... -s  (eq. exit_rotating_frame)
+template <int N>
+__device__ __forceinline__ void exit_frame(double wr, double Dt, Mat<N>& U) {
+  if (wr == 0.0) return;
+  const double beta = wr * Dt;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const double m = (N == 2) ? (a == 0 ? 0.5 : -0.5) : (double)(1 - a);
+    if (m == 0.0) continue;
+    double s, c;
+    sincos(-(m * beta), &s, &c);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const double xr = U.r[a][b], xi = U.i[a][b];
+      U.r[a][b] = fma(c, xr, -s * xi);
+      U.i[a][b] = fma(c, xi, s * xr);
+    }
+  }
+}
+
+}  // namespace mss

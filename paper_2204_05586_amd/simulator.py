@@ -1,0 +1,76 @@
+"""Python mirror of the paper's user API (Sec. "Compilation of integrator"):
+a ``Simulator`` built once from the user's choices (spin, field program,
+rotating frame, squaring count) and reused across ``evaluate`` calls with
+different sweep parameters, returning ``Results`` (time, state, time
+evolution operators).
+
+Field functions are field programs (lists of ``workloads.Term``) instead of
+compiled Python functions; ``params`` plays the role of sweep_parameters.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import native
+from .workloads import Problem, Term
+
+
+@dataclass
+class Results:
+    time: "object"             # torch float64 [K] on the device
+    state: "object"            # torch complex128 [K, N]: psi(t_k)
+    time_evolution: "object"   # torch complex128 [K, N, N] or None: U_k
+    state_final: "object"      # torch complex128 [N]: psi(t_start + K Dt)
+
+
+def grid_from_times(t_start: float, t_end: float, dt_integration: float, dt_output: float):
+    """Number of output intervals K and fine steps per interval L for a time
+    range (Sec. "Discretization and parallelization": t_k = t_0 + k Dt,
+    dt = Dt / L)."""
+    if not (dt_output > 0 and dt_integration > 0 and t_end > t_start):
+        raise ValueError("need t_end > t_start and positive time steps")
+    K = int(math.floor((t_end - t_start) / dt_output + 1e-9))
+    ratio = dt_output / dt_integration
+    L = int(round(ratio))
+    if L < 1 or abs(ratio - L) > 1e-9 * max(L, 1):
+        raise ValueError("dt_output must be an integer multiple of dt_integration")
+    if K < 1:
+        raise ValueError("time range shorter than one output step")
+    return K, L
+
+
+class Simulator:
+    """Spin-1/2 or spin-1 solver configured once, evaluated many times.
+
+    spin: 0.5 or 1.  terms: field program.  rotating_frame: per-interval
+    rotating frame (paper default: on).  n_squares: Lie-Trotter squaring
+    count tau for spin-1 (paper default 24)."""
+
+    def __init__(self, terms: Sequence[Term], spin: float = 1, rotating_frame: bool = True,
+                 n_squares: int = 24, device: str = "cuda"):
+        if spin not in (0.5, 1, 1.0):
+            raise ValueError("spin must be 0.5 or 1")
+        self.spin_twice = 1 if spin == 0.5 else 2
+        self.terms: List[Term] = list(terms)
+        self.rotating_frame = bool(rotating_frame)
+        self.n_squares = int(n_squares)
+        self.device = device
+
+    def problem(self, t_start, t_end, dt_integration, dt_output, params=None, psi0=None) -> Problem:
+        K, L = grid_from_times(t_start, t_end, dt_integration, dt_output)
+        return Problem(self.spin_twice, self.terms, float(t_start), float(dt_output), K, L,
+                       self.n_squares, self.rotating_frame,
+                       params=np.zeros(0) if params is None else params, psi0=psi0)
+
+    def evaluate(self, psi0, t_start: float, t_end: float, dt_integration: float,
+                 dt_output: float, params=None, keep_operators: bool = True,
+                 stream=None) -> Results:
+        prob = self.problem(t_start, t_end, dt_integration, dt_output, params, psi0)
+        native.validate(prob)
+        r = native.solve(prob, store_u=keep_operators, want_time=True, device=self.device,
+                         stream=stream)
+        return Results(r["time"], r["psi"], r["U"], r["psi_final"])

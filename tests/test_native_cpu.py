@@ -1,0 +1,96 @@
+"""Host-only checks of the C-ABI library: it loads, exports every function
+include/mss.h declares, validates problems before any launch, and sizes
+workspaces.  No GPU compute is called."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2204_05586_amd import native, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(mss_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    L = native.lib()
+    declared = _declared_functions()
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(native.EXPORTS) <= set(declared) | {"mss_last_error"}
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in native.version()
+    assert native.lib().mss_status_str(1).decode() == "MSS_E_INVALID"
+
+
+def _bad(prob, match):
+    with pytest.raises(native.MssError, match=match) as e:
+        native.validate(prob)
+    assert e.value.status == native.MSS_E_INVALID
+
+
+def test_validation_rejects_bad_problems():
+    good = W.spin_one_sensing(n_samples=10)
+    native.validate(good)
+    _bad(good.replace(spin_twice=3), "spin_twice")
+    _bad(good.replace(n_samples=0), "n_samples")
+    _bad(good.replace(n_fine=0), "n_fine")
+    _bad(good.replace(dt_out=0.0), "dt_out")
+    _bad(good.replace(dt_out=float("nan")), "dt_out")
+    _bad(good.replace(t_start=float("inf")), "t_start")
+    _bad(good.replace(n_squares=61), "n_squares")
+    half = W.spin_half_rabi(n_samples=10)
+    _bad(half.replace(terms=half.terms + [W.Term(W.CONST, W.Q, a=1.0)]), "quadrupole")
+    _bad(good.replace(terms=[W.Term(W.COS, W.X, a_slot=3)]), "slot")
+    _bad(good.replace(terms=[W.Term(9, W.X)]), "kind")
+    _bad(good.replace(terms=[W.Term(W.PWC, W.X, n_seg=4, seg_len=1.0, seg_a_slot=0)],
+                      params=np.zeros(3)), "segment slots")
+    _bad(good.replace(terms=[W.Term(W.PWC, W.X, n_seg=4, seg_len=0.0)]), "seg_len")
+    _bad(good.replace(terms=[W.Term(W.CONST, W.X, a=float("nan"))]), "finite")
+    _bad(good.replace(terms=[W.Term(W.CONST, W.X)] * 33), "terms")
+
+
+def test_workspace_sizes():
+    tile = 256
+    for spin_twice, K in [(1, 1), (1, 256), (2, 257), (2, 200_000), (2, 65_537)]:
+        N = spin_twice + 1
+        expect = 0
+        n = K
+        while n > tile:
+            n = -(-n // tile)
+            expect += -(-(n * 2 * N * N * 8) // 256) * 256 + -(-(n * 2 * N * 8) // 256) * 256
+        assert native.propagate_workspace_size(spin_twice, K) == expect
+        prob = W.random_problem(np.random.default_rng(0), spin_twice, K, 3)
+        assert native.workspace_size(prob, True) == expect
+        assert native.workspace_size(prob, False) == expect + -(-(K * N * N * 16) // 256) * 256
+
+
+def test_launch_plan_is_valid():
+    for prob in [W.spin_half_rabi(), W.spin_one_sensing(), W.spin_one_sensing(n_samples=7),
+                 W.spin_half_rabi(n_samples=1, n_fine=1)]:
+        S, B = native.plan_launch(prob)
+        assert S >= 1 and S & (S - 1) == 0 and S <= min(64, prob.n_fine)
+        assert B in (64, 128, 256)
+
+
+def test_solve_requires_buffers():
+    prob = W.spin_half_rabi(n_samples=4)
+    pk = native.PackedProblem(prob)
+    st = native.lib().mss_solve(pk.ref, None, None, None, None, None, None, None, 0, None)
+    assert st == native.MSS_E_INVALID
+    assert "psi0" in native.last_error()
