@@ -127,17 +127,64 @@ __device__ __forceinline__ void store_mat(double* __restrict__ p, const Mat<N>& 
 }
 
 // ---------------------------------------------------------------------------
-// sine / cosine of the tiny angles inside the exponentiators
+// sine and cosine
 // ---------------------------------------------------------------------------
-// Below 2^-10 the Taylor series to x^5 (sin) and x^6 (cos) is exact to
-// far below one ulp (next terms < 2e-22 relative); above it, ocml's sincos.
+// sincos_cw: Cody-Waite reduction x = k pi/2 + r with pi/2 split into three
+// doubles (P1, P2 with 32 significant bits so k P1 and k P2 are exact for
+// |k| < 2^20; P3 the rest), then the Taylor series of sin r to r^17 and of
+// cos r to r^16 on |r| <= pi/4 (truncation < 1e-17), rotated by the
+// quadrant k mod 4.  Beyond |x| = 1.5 * 2^20 the reduction is no longer
+// exact and ocml's sincos is used.
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+constexpr double kPio2_1 = 0x1.921fb54400000p+0;
+constexpr double kPio2_2 = 0x1.0b4611a600000p-34;
+constexpr double kPio2_3 = 0x1.3198a2e037073p-69;
+
+__device__ __forceinline__ void sincos_cw(double x, double* s, double* c) {
+  if (!(fabs(x) < 0x1.8p+20)) {
+    sincos(x, s, c);
+    return;
+  }
+  const double k = rint(x * kTwoOverPi);
+  double r = fma(-k, kPio2_1, x);
+  r = fma(-k, kPio2_2, r);
+  r = fma(-k, kPio2_3, r);
+  const double r2 = r * r;
+  double ps = 0x1.952c77030ad4ap-49;          //  1/17!
+  ps = fma(ps, r2, -0x1.ae7f3e733b81fp-41);   // -1/15!
+  ps = fma(ps, r2, 0x1.6124613a86d09p-33);    //  1/13!
+  ps = fma(ps, r2, -0x1.ae64567f544e4p-26);   // -1/11!
+  ps = fma(ps, r2, 0x1.71de3a556c734p-19);    //  1/9!
+  ps = fma(ps, r2, -0x1.a01a01a01a01ap-13);   // -1/7!
+  ps = fma(ps, r2, 0x1.1111111111111p-7);     //  1/5!
+  ps = fma(ps, r2, -0x1.5555555555555p-3);    // -1/3!
+  const double sn = fma(r * r2, ps, r);
+  double pc = 0x1.ae7f3e733b81fp-45;          //  1/16!
+  pc = fma(pc, r2, -0x1.93974a8c07c9dp-37);   // -1/14!
+  pc = fma(pc, r2, 0x1.1eed8eff8d898p-29);    //  1/12!
+  pc = fma(pc, r2, -0x1.27e4fb7789f5cp-22);   // -1/10!
+  pc = fma(pc, r2, 0x1.a01a01a01a01ap-16);    //  1/8!
+  pc = fma(pc, r2, -0x1.6c16c16c16c17p-10);   // -1/6!
+  pc = fma(pc, r2, 0x1.5555555555555p-5);     //  1/4!
+  pc = fma(pc, r2, -0.5);                     // -1/2!
+  const double cn = fma(r2, pc, 1.0);
+  const int q = ((int)k) & 3;
+  const double s1 = (q & 1) ? cn : sn;
+  const double c1 = (q & 1) ? sn : cn;
+  *s = (q & 2) ? -s1 : s1;
+  *c = ((q + 1) & 2) ? -c1 : c1;
+}
+
+// Tiny angles inside the exponentiators: below 2^-10 the Taylor series to
+// x^5 (sin) and x^6 (cos) is exact to far below one ulp (next terms
+// < 2e-22 relative); above it, sincos_cw.
 __device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
   if (fabs(x) < 0x1p-10) {
     const double x2 = x * x;
     *s = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
     *c = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
   } else {
-    sincos(x, s, c);
+    sincos_cw(x, s, c);
   }
 }
 
@@ -156,7 +203,7 @@ __device__ __forceinline__ void exp_half(const double th[4], int /*tau*/, Mat<2>
     S = 0.5 * fma(x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), 1.0);
   } else {
     double s;
-    sincos(x, &s, &c);
+    sincos_cw(x, &s, &c);
     S = s / big;
   }
   E.r[0][0] = c;           E.i[0][0] = -S * th[2];
@@ -227,16 +274,27 @@ __device__ __forceinline__ void lie_trotter_residual(const double th[4], int tau
   }
 }
 
-// tau residual squarings a <- (a + 2I) a, then I + a.
+// One residual squaring y = (x + 2I) x: only the real diagonal of the
+// left factor differs from x.
+__device__ __forceinline__ void residual_square(const Mat<3>& x, Mat<3>& y) {
+  Mat<3> b = x;
+  b.r[0][0] += 2.0;
+  b.r[1][1] += 2.0;
+  b.r[2][2] += 2.0;
+  matmul<3>(b, x, y);
+}
+
+// tau residual squarings a <- (a + 2I) a, then I + a.  Two squarings per
+// trip alternate between two register sets, so nothing is copied.
 __device__ __forceinline__ void exp_one(const double th[4], int tau, Mat<3>& E) {
   Mat<3> a;
   lie_trotter_residual(th, tau, a);
-  for (int s = 0; s < tau; ++s) {
-    Mat<3> b = a;
-    b.r[0][0] += 2.0;
-    b.r[1][1] += 2.0;
-    b.r[2][2] += 2.0;
-    matmul<3>(b, a, E);
+  for (int s = 0; s + 2 <= tau; s += 2) {
+    residual_square(a, E);
+    residual_square(E, a);
+  }
+  if (tau & 1) {
+    residual_square(a, E);
     a = E;
   }
   E = a;
@@ -288,7 +346,9 @@ __device__ __forceinline__ void field_eval(const FieldProgram& fp, const double*
       const double ft = fr * t;
       const double x = kTwoPi * ft;
       const double arg = x + ph;
-      v = amp * ((kind == MSS_TERM_COS || kind == MSS_TERM_PWC_COS) ? cos(arg) : sin(arg));
+      double sn, cs;
+      sincos_cw(arg, &sn, &cs);
+      v = amp * ((kind == MSS_TERM_COS || kind == MSS_TERM_PWC_COS) ? cs : sn);
     }
     switch (tm.comp) {
       case 0: fx = fx + v; break;
@@ -317,7 +377,7 @@ __device__ __forceinline__ void cf4_angles(const FieldProgram& fp, const double*
     if (wr != 0.0) {
       // (w_x + i w_y) e^{-i wr tau_i}
       double s, c;
-      sincos(wr * tau_i, &s, &c);
+      sincos_cw(wr * tau_i, &s, &c);
       const double xr = w[i][0] * c + w[i][1] * s;
       const double xi = w[i][1] * c - w[i][0] * s;
       w[i][0] = xr;
@@ -358,7 +418,7 @@ __device__ __forceinline__ void exit_frame(double wr, double Dt, Mat<N>& U) {
     const double m = (N == 2) ? (a == 0 ? 0.5 : -0.5) : (double)(1 - a);
     if (m == 0.0) continue;
     double s, c;
-    sincos(-(m * beta), &s, &c);
+    sincos_cw(-(m * beta), &s, &c);
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       const double xr = U.r[a][b], xi = U.i[a][b];
