@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the solver path on one MI355X.
 
-One step = the whole path over one simulation: the integrator (interval
-operators U_k from CF4 fine steps in the rotating frame, frame exit) and the
-ordered product (states psi_k), both through the C ABI.  Inputs and outputs
+Default workload: 4096 spin-1 sensing simulations of uneven length (10-100
+ms at 5e-7 s output steps, 10 CF4 steps per interval, tau = 28, rotating
+frame) run as one batch: the persistent integrator (interval operators from
+CF4 fine steps) followed by the segmented scan (states psi_k), both through
+the C ABI.  One step = one pass over the whole batch.  Inputs and outputs
 stay resident in HBM; the timed region starts after they are allocated.
+
+Also measured in the same run: the plain path (one simulation per launch
+sequence) on the single spin-1 sensing simulation, and the batch replayed as
+one captured HIP graph.
 
 Prints one JSON line: CF4 fine steps/s, the integrator's roofline figures
 (algorithmic FP64 flops / measured kernel time vs the 78.6 TFLOP/s FP64
 vector peak) and the CPU oracle's rate on a bounded sample.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import statistics
 import sys
@@ -23,6 +29,22 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 
+# HBM traffic of the integrator per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes, calibrated against a 1 GiB copy (FETCH x 2.000, WRITE x 1.000), keyed by
+# the hash of the kernel sources it was taken with: reported only while the
+# sources are unchanged.
+MEASURED_TRAFFIC = {}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2204_05586_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
 
 def spin_one_flops_per_fine_step(tau: int) -> int:
     """Algorithmic FP64 flops of one spin-1 CF4 fine step: two Lie-Trotter
@@ -31,112 +53,199 @@ def spin_one_flops_per_fine_step(tau: int) -> int:
     return 2 * tau * 216 + 2 * 216
 
 
-def make_workload(name: str):
-    from paper_2204_05586_amd import workloads as W
-    if name == "spin_one_sensing":
-        return W.spin_one_sensing()
-    if name == "spin_half_rabi":
-        return W.spin_half_rabi()
-    raise SystemExit(f"unknown workload {name}")
-
-
-def cpu_baseline(prob, seconds: float) -> dict:
-    """The CPU oracle on a bounded prefix of the same simulation."""
+def cpu_baseline(problems, seconds: float) -> dict:
+    """The CPU oracle on a bounded sample of the workload's simulations."""
     from oracle import oracle
     threads = oracle.get_threads()
-    k = min(prob.n_samples, 2000)
-    t0 = time.perf_counter()
-    oracle.solve(prob.replace(n_samples=k))
+    done_steps, used, t0 = 0, 0, time.perf_counter()
+    for p in problems:
+        oracle.solve(p)
+        done_steps += p.fine_steps
+        used += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
     dt = time.perf_counter() - t0
-    k = int(min(prob.n_samples, max(k, k * seconds / max(dt, 1e-6))))
-    sample = prob.replace(n_samples=k)
-    t0 = time.perf_counter()
-    oracle.solve(sample)
-    dt = time.perf_counter() - t0
-    return {"value": sample.fine_steps / dt, "unit": "fine_steps/s", "cores": threads,
+    return {"value": round(done_steps / dt, 1), "unit": "fine_steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {k} of {prob.n_samples} intervals of {prob.name} "
-                      f"({sample.fine_steps} fine steps, {dt:.1f} s, {threads} threads)"}
+            "sample": f"{used} of {len(problems)} simulations ({done_steps} fine steps, "
+                      f"{dt:.1f} s, {threads} OpenMP threads over intervals)"}
+
+
+def bench_plain(prob, steps: int, warmup: int) -> dict:
+    import torch
+    from paper_2204_05586_amd import native
+    K, N = prob.n_samples, prob.dim
+    params = native.device_params(prob)
+    psi0 = native.device_state(prob.psi0)
+    U = torch.empty((K, N, N), dtype=torch.complex128, device="cuda")
+    psi = torch.empty((K, N), dtype=torch.complex128, device="cuda")
+    fin = torch.empty((N,), dtype=torch.complex128, device="cuda")
+    ws = native.alloc_workspace(native.propagate_workspace_size(prob.spin_twice, K))
+    launch = native.plan_launch(prob)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        native.integrate(prob, params, U, launch=launch, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        native.propagate(prob.spin_twice, U, psi0, psi, fin, ws, stream=stream)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e in evs:
+        step(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    integ = [e[0].elapsed_time(e[1]) for e in evs]
+    prop = [e[1].elapsed_time(e[2]) for e in evs]
+    return {"workload": prob.name, "fine_steps": prob.fine_steps,
+            "value": prob.fine_steps * steps / wall, "ms_per_step": wall / steps * 1e3,
+            "integrate_ms": statistics.mean(integ), "propagate_ms": statistics.mean(prop),
+            "launch": {"slices": launch[0], "block": launch[1]}, "tau": prob.n_squares}
+
+
+def bench_batched(problems, steps: int, warmup: int, graph_reps: int) -> dict:
+    import torch
+    from paper_2204_05586_amd import native
+    plan = native.BatchPlan(problems)
+    bufs = plan.allocate(store_u=False)
+    stream = torch.cuda.current_stream()
+    fine = sum(p.fine_steps for p in problems)
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        plan.integrate(bufs, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        plan.propagate(bufs, stream=stream)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e in evs:
+        step(e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    integ = [e[0].elapsed_time(e[1]) for e in evs]
+    prop = [e[1].elapsed_time(e[2]) for e in evs]
+    info = plan.info()
+    plan.close()
+    out = {"value": fine * steps / wall, "ms_per_step": wall / steps * 1e3,
+           "integrate_ms": statistics.mean(integ), "propagate_ms": statistics.mean(prop),
+           "fine_steps": fine, "info": info}
+    if graph_reps > 0:
+        gplan = native.BatchPlan(problems, use_graph=True)
+        gplan.run(bufs, stream=stream)  # capture + first replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(graph_reps):
+            gplan.run(bufs, stream=stream)
+        torch.cuda.synchronize()
+        out["graph_ms_per_step"] = (time.perf_counter() - t0) / graph_reps * 1e3
+        gplan.close()
+    del bufs
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="spin_one_sensing")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched_sensing",
+                    choices=["batched_sensing", "spin_one_sensing", "spin_half_rabi"])
+    ap.add_argument("--n-sims", type=int, default=4096, help="batch size of batched_sensing")
+    ap.add_argument("--plain-steps", type=int, default=20)
+    ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
                     help="target CPU seconds of the oracle sample (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (single-GPU solver path); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py: this build measures one GPU only; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_2204_05586_amd import native
+    from paper_2204_05586_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    prob = make_workload(args.workload)
-    K, N, L = prob.n_samples, prob.dim, prob.n_fine
-    dev = "cuda"
-    params = native.device_params(prob, dev)
-    psi0 = native.device_state(prob.psi0, dev)
-    U = torch.empty((K, N, N), dtype=torch.complex128, device=dev)
-    psi = torch.empty((K, N), dtype=torch.complex128, device=dev)
-    fin = torch.empty((N,), dtype=torch.complex128, device=dev)
-    ws = native.alloc_workspace(native.propagate_workspace_size(prob.spin_twice, K), dev)
-    launch = native.plan_launch(prob)
-    stream = torch.cuda.current_stream()
+    torch.cuda.init()
+    src_hash = kernel_source_hash()
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        native.integrate(prob, params, U, launch=launch, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
-        native.propagate(prob.spin_twice, U, psi0, psi, fin, ws, stream=stream)
-        if ev is not None:
-            ev[2].record(stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(events[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    integ_ms = [e[0].elapsed_time(e[1]) for e in events]
-    prop_ms = [e[1].elapsed_time(e[2]) for e in events]
-    fine_steps = prob.fine_steps
-    value = fine_steps * args.steps / wall
+    if args.workload == "batched_sensing":
+        problems = W.batched_sensing(seed=2, n_sims=args.n_sims)
+        tau = problems[0].n_squares
+        res = bench_batched(problems, args.steps, args.warmup, args.graph_reps)
+        kernel = "batch_integrate_kernel"
+        plain = bench_plain(W.spin_one_sensing(), args.plain_steps, 3)
+        value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
+            res["fine_steps"]
+        config = {"workload": f"batched_sensing: {len(problems)} spin-1 simulations, seed 2, "
+                              f"durations U(10,100) ms, dt_out 5e-7 s",
+                  "mode": "batched (persistent integrator + segmented scan, eager launches)",
+                  "n_sims": len(problems), "total_intervals": res["info"]["total_samples"],
+                  "n_fine": 10, "fine_steps": fine, "n_squares": tau, "rotating_frame": True,
+                  "work_items": res["info"]["n_items"], "grid_blocks": res["info"]["grid_blocks"],
+                  "scan_levels": res["info"]["scan_levels"]}
+        extra = {"integrate_ms_mean": round(integ_ms, 3),
+                 "propagate_ms_mean": round(res["propagate_ms"], 3),
+                 "graph_ms_per_step": round(res.get("graph_ms_per_step", 0.0), 3) or None,
+                 "plain": {k: (round(v, 4) if isinstance(v, float) else v)
+                           for k, v in plain.items()},
+                 "batched_over_plain": round(value / plain["value"], 3)}
+        base_problems = problems
+    else:
+        prob = W.spin_one_sensing() if args.workload == "spin_one_sensing" else W.spin_half_rabi()
+        tau = prob.n_squares
+        res = bench_plain(prob, args.steps, args.warmup)
+        kernel = "integrate_kernel<3>" if prob.spin_twice == 2 else "integrate_kernel<2>"
+        value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
+            res["fine_steps"]
+        config = {"workload": prob.name, "mode": "plain (one simulation per launch sequence)",
+                  "n_samples": prob.n_samples, "n_fine": prob.n_fine, "fine_steps": fine,
+                  "n_squares": tau, "rotating_frame": prob.rotating_frame,
+                  "launch": res["launch"]}
+        extra = {"integrate_ms_mean": round(integ_ms, 4),
+                 "propagate_ms_mean": round(res["propagate_ms"], 4)}
+        base_problems = [prob]
 
     roofline = None
-    if prob.spin_twice == 2:
-        flops = spin_one_flops_per_fine_step(prob.n_squares) * fine_steps
-        achieved = flops / (statistics.mean(integ_ms) * 1e-3) / 1e12
+    if args.workload != "spin_half_rabi":
+        flops = spin_one_flops_per_fine_step(tau) * fine
+        achieved = flops / (integ_ms * 1e-3) / 1e12
+        traffic = MEASURED_TRAFFIC.get((kernel, args.workload))
         roofline = {"bound": "alu", "achieved": round(achieved, 3),
                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-                    "kernel": "integrate_kernel<3>",
-                    "flops_per_launch": flops,
-                    "kernel_ms_mean": round(statistics.mean(integ_ms), 4)}
+                    "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
+                    "traffic": (traffic["bytes"] if traffic and traffic["src"] == src_hash
+                                else None),
+                    "kernel": kernel, "flops_per_launch": flops,
+                    "kernel_ms_mean": round(integ_ms, 4)}
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 8
-        a = torch.ones(n, dtype=torch.float64, device=dev)
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
 
-    base = cpu_baseline(prob, args.cpu_baseline_seconds) if args.cpu_baseline_seconds > 0 else None
+    base = (cpu_baseline(base_problems, args.cpu_baseline_seconds)
+            if args.cpu_baseline_seconds > 0 else None)
 
     out = {
         "metric": "CF4 fine steps/sec (spin-1, FP64) batched vs plain on 1 GPU; p50/p99 latency",
@@ -145,21 +254,17 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": prob.name, "mode": "plain (one simulation per launch sequence)",
-                   "spin": "1" if prob.spin_twice == 2 else "1/2", "n_samples": K,
-                   "n_fine": L, "fine_steps": fine_steps, "n_squares": prob.n_squares,
-                   "rotating_frame": prob.rotating_frame, "launch": {"slices": launch[0],
-                                                                      "block": launch[1]}},
-        "integrate_ms_mean": round(statistics.mean(integ_ms), 4),
-        "propagate_ms_mean": round(statistics.mean(prop_ms), 4),
+        "config": config,
+        **extra,
         "roofline": roofline,
         "cpu_baseline": base,
+        "kernel_src": src_hash,
     }
     print(json.dumps(out), flush=True)
 

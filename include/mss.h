@@ -113,7 +113,7 @@ typedef struct mss_problem {
 /* Launch shape of the integrator.  slices: lanes cooperating on one
  * interval (power of two, 1..64, <= n_fine); each lane takes a contiguous
  * run of fine steps and the partial products are combined in order.
- * block: threads per workgroup (64, 128, 256, 512 or 1024).
+ * block: threads per workgroup (64, 128 or 256).
  * Zero fields mean "choose" (mss_plan_launch). */
 typedef struct mss_launch {
   int32_t slices;
@@ -167,6 +167,79 @@ mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
 mss_status mss_solve(const mss_problem* p, const double* params, const double* psi0, double* U,
                      double* psi, double* psi_final, double* time, void* ws, size_t ws_bytes,
                      void* stream);
+
+/* ---- batches ------------------------------------------------------------
+ * Many independent simulations (uneven K, mixed spin allowed) in one
+ * persistent integrator launch and one segmented scan.  Sweeps over
+ * parameters (the paper's use of one compiled simulator for many
+ * evaluate() calls, Sec. "Compilation of integrator") become one batch.
+ *
+ * Packed layout (complex units), simulation i in order:
+ *   psi0 / psi_final  N_i entries at psi0_off[i]
+ *   psi               K_i N_i entries at state_off[i]
+ *   U                 K_i N_i^2 entries at op_off[i]
+ * mss_batch_layout returns these offsets (n + 1 entries, the last = total).
+ * params: one device array; simulation i reads its n_params values from
+ * index param_off[i].
+ *
+ * A plan owns device descriptors (uploaded synchronously at creation) and,
+ * with use_graph, one instantiated HIP graph of the whole batch; it is not
+ * thread-safe.  Work enqueued by mss_batch_run reads the plan's
+ * descriptors: destroy the plan only after that work has completed. */
+typedef struct mss_batch_plan mss_batch_plan;
+
+typedef struct mss_batch_options {
+  int32_t slices_spin_half; /* lanes per spin-1/2 interval, power of two <= 64, 0: choose */
+  int32_t slices_spin_one;  /* lanes per spin-1 interval, 0: choose */
+  int32_t waves_per_simd;   /* persistent grid: resident waves per SIMD (0: 2) */
+  int32_t use_graph;        /* 1: capture the batch as one HIP graph, replayed while the
+                               buffer pointers stay the same */
+} mss_batch_options;
+
+typedef struct mss_batch_info_t {
+  int32_t n_sims;
+  int32_t scan_levels;
+  int32_t grid_blocks;      /* 256-thread workgroups of the persistent integrator */
+  int32_t pad;
+  int64_t n_items;          /* work items (one wave's worth of intervals each) */
+  int64_t total_samples;    /* sum of K_i */
+} mss_batch_info_t;
+
+/* Validate every problem (as mss_validate) and build a plan.  problems and
+ * param_off are host arrays of n entries; param_off may be NULL when no
+ * simulation has parameters.  options may be NULL (all defaults). */
+mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const int64_t* param_off,
+                                 const mss_batch_options* options, mss_batch_plan** out);
+
+/* Packed offsets (host arrays of n + 1 entries each; any may be NULL). */
+mss_status mss_batch_layout(const mss_batch_plan* plan, int64_t* psi0_off, int64_t* state_off,
+                            int64_t* op_off);
+
+/* Device workspace bytes for mss_batch_run; store_u = 0 when U is NULL. */
+mss_status mss_batch_workspace_size(const mss_batch_plan* plan, int32_t store_u, size_t* bytes);
+
+/* Shape of the planned launch. */
+mss_status mss_batch_info(const mss_batch_plan* plan, mss_batch_info_t* info);
+
+/* Run the batch: operators (into U, or the workspace when U is NULL), then
+ * states psi and (optional) psi_final, all device arrays in the packed
+ * layout.  Asynchronous on `stream`. */
+mss_status mss_batch_run(mss_batch_plan* plan, const double* params, const double* psi0,
+                         double* psi, double* psi_final, double* U, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* The two halves of mss_batch_run, always launched eagerly (no graph):
+ * the persistent integrator (operators into U, or the workspace when U is
+ * NULL) and the segmented scan that reads them.  Pass the same U / ws to
+ * both. */
+mss_status mss_batch_integrate(mss_batch_plan* plan, const double* params, double* U, void* ws,
+                               size_t ws_bytes, void* stream);
+mss_status mss_batch_propagate(mss_batch_plan* plan, const double* psi0, double* psi,
+                               double* psi_final, const double* U, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* Free the plan (its graph, stream and descriptors). */
+void mss_batch_plan_destroy(mss_batch_plan* plan);
 
 #ifdef __cplusplus
 }

@@ -13,10 +13,12 @@
 using namespace mss;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-mss_status fail(mss_status s, const char* fmt, ...) {
+namespace mss {
+
+mss_status api_fail(mss_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -26,14 +28,20 @@ mss_status fail(mss_status s, const char* fmt, ...) {
   return s;
 }
 
-mss_status ok() {
+mss_status api_ok() {
   g_err.clear();
   return MSS_OK;
 }
 
-mss_status hip_fail(hipError_t e, const char* what) {
-  return fail(MSS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+mss_status api_hip_fail(hipError_t e, const char* what) {
+  return api_fail(MSS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+std::string api_last_error_copy() { return g_err; }
+
+}  // namespace mss
+
+namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -123,53 +131,64 @@ ScanLevels plan_scan(int N, int64_t K) {
 }
 
 mss_status validate_problem(const mss_problem* p) {
-  if (!p) return fail(MSS_E_INVALID, "problem is NULL");
+  if (!p) return api_fail(MSS_E_INVALID, "problem is NULL");
   if (p->spin_twice != 1 && p->spin_twice != 2)
-    return fail(MSS_E_INVALID, "spin_twice must be 1 (spin-1/2) or 2 (spin-1), got %d",
+    return api_fail(MSS_E_INVALID, "spin_twice must be 1 (spin-1/2) or 2 (spin-1), got %d",
                 p->spin_twice);
   if (p->n_terms < 0 || p->n_terms > MSS_MAX_TERMS)
-    return fail(MSS_E_INVALID, "n_terms must be in [0, %d], got %d", MSS_MAX_TERMS, p->n_terms);
-  if (p->n_terms > 0 && !p->terms) return fail(MSS_E_INVALID, "terms is NULL");
-  if (p->n_params < 0) return fail(MSS_E_INVALID, "n_params must be >= 0");
-  if (p->n_fine < 1) return fail(MSS_E_INVALID, "n_fine (L) must be >= 1, got %d", p->n_fine);
+    return api_fail(MSS_E_INVALID, "n_terms must be in [0, %d], got %d", MSS_MAX_TERMS, p->n_terms);
+  if (p->n_terms > 0 && !p->terms) return api_fail(MSS_E_INVALID, "terms is NULL");
+  if (p->n_params < 0) return api_fail(MSS_E_INVALID, "n_params must be >= 0");
+  if (p->n_fine < 1) return api_fail(MSS_E_INVALID, "n_fine (L) must be >= 1, got %d", p->n_fine);
   if (p->n_samples < 1)
-    return fail(MSS_E_INVALID, "n_samples (K) must be >= 1, got %lld", (long long)p->n_samples);
+    return api_fail(MSS_E_INVALID, "n_samples (K) must be >= 1, got %lld", (long long)p->n_samples);
   if (p->n_samples > ((int64_t)1 << 40))
-    return fail(MSS_E_INVALID, "n_samples (K) too large: %lld", (long long)p->n_samples);
-  if (!finite(p->t_start)) return fail(MSS_E_INVALID, "t_start is not finite");
+    return api_fail(MSS_E_INVALID, "n_samples (K) too large: %lld", (long long)p->n_samples);
+  if (!finite(p->t_start)) return api_fail(MSS_E_INVALID, "t_start is not finite");
   if (!finite(p->dt_out) || !(p->dt_out > 0.0))
-    return fail(MSS_E_INVALID, "dt_out must be finite and > 0");
+    return api_fail(MSS_E_INVALID, "dt_out must be finite and > 0");
   if (!finite(p->t_start + (double)p->n_samples * p->dt_out))
-    return fail(MSS_E_INVALID, "t_start + K * dt_out is not finite");
+    return api_fail(MSS_E_INVALID, "t_start + K * dt_out is not finite");
   if (p->n_squares < 0 || p->n_squares > MSS_MAX_SQUARES)
-    return fail(MSS_E_INVALID, "n_squares (tau) must be in [0, %d], got %d", MSS_MAX_SQUARES,
+    return api_fail(MSS_E_INVALID, "n_squares (tau) must be in [0, %d], got %d", MSS_MAX_SQUARES,
                 p->n_squares);
   if (p->rotating_frame != 0 && p->rotating_frame != 1)
-    return fail(MSS_E_INVALID, "rotating_frame must be 0 or 1");
+    return api_fail(MSS_E_INVALID, "rotating_frame must be 0 or 1");
   for (int i = 0; i < p->n_terms; ++i) {
     const mss_term& t = p->terms[i];
     if (t.kind < MSS_TERM_CONST || t.kind > MSS_TERM_PWC_SIN)
-      return fail(MSS_E_INVALID, "term %d: unknown kind %d", i, t.kind);
-    if (t.comp < 0 || t.comp > 3) return fail(MSS_E_INVALID, "term %d: comp must be 0..3", i);
+      return api_fail(MSS_E_INVALID, "term %d: unknown kind %d", i, t.kind);
+    if (t.comp < 0 || t.comp > 3) return api_fail(MSS_E_INVALID, "term %d: comp must be 0..3", i);
     if (t.comp == MSS_Q && p->spin_twice != 2)
-      return fail(MSS_E_INVALID, "term %d: the quadrupole component needs spin-1", i);
+      return api_fail(MSS_E_INVALID, "term %d: the quadrupole component needs spin-1", i);
     if (!finite(t.a) || !finite(t.f) || !finite(t.phi))
-      return fail(MSS_E_INVALID, "term %d: a, f, phi must be finite", i);
-    if (isnan(t.t_on) || isnan(t.t_off)) return fail(MSS_E_INVALID, "term %d: NaN window", i);
+      return api_fail(MSS_E_INVALID, "term %d: a, f, phi must be finite", i);
+    if (isnan(t.t_on) || isnan(t.t_off)) return api_fail(MSS_E_INVALID, "term %d: NaN window", i);
     if (!slot_ok(t.a_slot, 1, p->n_params) || !slot_ok(t.f_slot, 1, p->n_params) ||
         !slot_ok(t.phi_slot, 1, p->n_params))
-      return fail(MSS_E_INVALID, "term %d: parameter slot beyond n_params = %d", i, p->n_params);
+      return api_fail(MSS_E_INVALID, "term %d: parameter slot beyond n_params = %d", i, p->n_params);
     if (t.kind >= MSS_TERM_PWC) {
-      if (t.n_seg < 1) return fail(MSS_E_INVALID, "term %d: n_seg must be >= 1", i);
+      if (t.n_seg < 1) return api_fail(MSS_E_INVALID, "term %d: n_seg must be >= 1", i);
       if (!finite(t.seg_t0) || !finite(t.seg_len) || !(t.seg_len > 0.0))
-        return fail(MSS_E_INVALID, "term %d: seg_t0 finite and seg_len > 0 required", i);
+        return api_fail(MSS_E_INVALID, "term %d: seg_t0 finite and seg_len > 0 required", i);
       if (!slot_ok(t.seg_a_slot, t.n_seg, p->n_params) ||
           !slot_ok(t.seg_phi_slot, t.n_seg, p->n_params))
-        return fail(MSS_E_INVALID, "term %d: segment slots beyond n_params = %d", i, p->n_params);
+        return api_fail(MSS_E_INVALID, "term %d: segment slots beyond n_params = %d", i, p->n_params);
     }
   }
   return MSS_OK;
 }
+
+}  // namespace
+
+namespace mss {
+int api_device_cu_count() { return device_cu_count(); }
+int api_plan_slices(int64_t K, int32_t L, int cu) { return plan_slices(K, L, cu); }
+int api_ilog2(int x) { return ilog2(x); }
+mss_status api_validate_problem(const mss_problem* p) { return validate_problem(p); }
+}  // namespace mss
+
+namespace {
 
 mss_status resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block) {
   int S = in ? in->slices : 0;
@@ -177,12 +196,12 @@ mss_status resolve_launch(const mss_problem* p, const mss_launch* in, int* slice
   if (S == 0) S = plan_slices(p->n_samples, p->n_fine, device_cu_count());
   if (B == 0) B = 256;
   if (S < 1 || S > 64 || (S & (S - 1)) != 0 || S > p->n_fine)
-    return fail(MSS_E_INVALID, "launch.slices must be a power of two in [1, min(64, L)], got %d",
+    return api_fail(MSS_E_INVALID, "launch.slices must be a power of two in [1, min(64, L)], got %d",
                 S);
   if (B != 64 && B != 128 && B != 256)
-    return fail(MSS_E_INVALID, "launch.block must be 64, 128 or 256, got %d", B);
+    return api_fail(MSS_E_INVALID, "launch.block must be 64, 128 or 256, got %d", B);
   const int64_t grid = (p->n_samples * S + B - 1) / B;
-  if (grid > 0x7fffffffLL) return fail(MSS_E_INVALID, "grid too large");
+  if (grid > 0x7fffffffLL) return api_fail(MSS_E_INVALID, "grid too large");
   *slices = S;
   *block = B;
   return MSS_OK;
@@ -211,45 +230,45 @@ const char* mss_version(void) { return "mss 0.1 gfx950"; }
 
 mss_status mss_validate(const mss_problem* p) {
   mss_status s = validate_problem(p);
-  return s == MSS_OK ? ok() : s;
+  return s == MSS_OK ? api_ok() : s;
 }
 
 mss_status mss_plan_launch(const mss_problem* p, mss_launch* out) {
   mss_status s = validate_problem(p);
   if (s != MSS_OK) return s;
-  if (!out) return fail(MSS_E_INVALID, "out is NULL");
+  if (!out) return api_fail(MSS_E_INVALID, "out is NULL");
   int S, B;
   if ((s = resolve_launch(p, nullptr, &S, &B)) != MSS_OK) return s;
   out->slices = S;
   out->block = B;
-  return ok();
+  return api_ok();
 }
 
 mss_status mss_propagate_workspace_size(int32_t spin_twice, int64_t n_samples, size_t* bytes) {
-  if (spin_twice != 1 && spin_twice != 2) return fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
-  if (n_samples < 1) return fail(MSS_E_INVALID, "n_samples must be >= 1");
-  if (!bytes) return fail(MSS_E_INVALID, "bytes is NULL");
+  if (spin_twice != 1 && spin_twice != 2) return api_fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
+  if (n_samples < 1) return api_fail(MSS_E_INVALID, "n_samples must be >= 1");
+  if (!bytes) return api_fail(MSS_E_INVALID, "bytes is NULL");
   *bytes = plan_scan(spin_twice + 1, n_samples).bytes;
-  return ok();
+  return api_ok();
 }
 
 mss_status mss_workspace_size(const mss_problem* p, int32_t store_u, size_t* bytes) {
   mss_status s = validate_problem(p);
   if (s != MSS_OK) return s;
-  if (!bytes) return fail(MSS_E_INVALID, "bytes is NULL");
+  if (!bytes) return api_fail(MSS_E_INVALID, "bytes is NULL");
   const int N = p->spin_twice + 1;
   size_t b = plan_scan(N, p->n_samples).bytes;
   if (!store_u) b += align256((size_t)p->n_samples * 2 * N * N * sizeof(double));
   *bytes = b;
-  return ok();
+  return api_ok();
 }
 
 mss_status mss_integrate(const mss_problem* p, const double* params, double* U, double* time,
                          const mss_launch* launch, void* stream) {
   mss_status s = validate_problem(p);
   if (s != MSS_OK) return s;
-  if (!U) return fail(MSS_E_INVALID, "U is NULL");
-  if (p->n_params > 0 && !params) return fail(MSS_E_INVALID, "params is NULL but n_params > 0");
+  if (!U) return api_fail(MSS_E_INVALID, "U is NULL");
+  if (p->n_params > 0 && !params) return api_fail(MSS_E_INVALID, "params is NULL but n_params > 0");
   int S, B;
   if ((s = resolve_launch(p, launch, &S, &B)) != MSS_OK) return s;
   IntegrateArgs a;
@@ -268,20 +287,20 @@ mss_status mss_integrate(const mss_problem* p, const double* params, double* U, 
   a.frame = p->rotating_frame;
   a.slices_log2 = ilog2(S);
   hipError_t e = launch_integrate(p->spin_twice + 1, a, B, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "integrate launch");
-  return ok();
+  if (e != hipSuccess) return api_hip_fail(e, "integrate launch");
+  return api_ok();
 }
 
 mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
                          const double* psi0, double* psi, double* psi_final, void* ws,
                          size_t ws_bytes, void* stream) {
-  if (spin_twice != 1 && spin_twice != 2) return fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
-  if (n_samples < 1) return fail(MSS_E_INVALID, "n_samples must be >= 1");
-  if (!U || !psi0 || !psi) return fail(MSS_E_INVALID, "U, psi0 and psi are required");
+  if (spin_twice != 1 && spin_twice != 2) return api_fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
+  if (n_samples < 1) return api_fail(MSS_E_INVALID, "n_samples must be >= 1");
+  if (!U || !psi0 || !psi) return api_fail(MSS_E_INVALID, "U, psi0 and psi are required");
   const int N = spin_twice + 1;
   const ScanLevels lv = plan_scan(N, n_samples);
   if (lv.bytes > 0 && (!ws || ws_bytes < lv.bytes))
-    return fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", lv.bytes,
+    return api_fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", lv.bytes,
                 ws ? ws_bytes : (size_t)0);
   hipStream_t st = (hipStream_t)stream;
   char* w = (char*)ws;
@@ -291,7 +310,7 @@ mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
   hipError_t e;
   for (int l = 0; l < lv.n_levels; ++l) {
     e = launch_scan_reduce(N, M[l], lv.n[l], (double*)M[l + 1], st);
-    if (e != hipSuccess) return hip_fail(e, "scan reduce launch");
+    if (e != hipSuccess) return api_hip_fail(e, "scan reduce launch");
   }
   // top level: one tile entered with psi0
   for (int l = lv.n_levels; l >= 0; --l) {
@@ -299,9 +318,9 @@ mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
     double* before = (l == 0) ? psi : (double*)(w + lv.state_off[l]);
     double* after = (l == 0) ? psi_final : nullptr;
     e = launch_scan_apply(N, M[l], lv.n[l], start, before, after, st);
-    if (e != hipSuccess) return hip_fail(e, "scan apply launch");
+    if (e != hipSuccess) return api_hip_fail(e, "scan apply launch");
   }
-  return ok();
+  return api_ok();
 }
 
 mss_status mss_solve(const mss_problem* p, const double* params, const double* psi0, double* U,
@@ -309,12 +328,12 @@ mss_status mss_solve(const mss_problem* p, const double* params, const double* p
                      void* stream) {
   mss_status s = validate_problem(p);
   if (s != MSS_OK) return s;
-  if (!psi0 || !psi) return fail(MSS_E_INVALID, "psi0 and psi are required");
+  if (!psi0 || !psi) return api_fail(MSS_E_INVALID, "psi0 and psi are required");
   const int N = p->spin_twice + 1;
   size_t need = 0;
   if ((s = mss_workspace_size(p, U != nullptr, &need)) != MSS_OK) return s;
   if (need > 0 && (!ws || ws_bytes < need))
-    return fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", need,
+    return api_fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", need,
                 ws ? ws_bytes : (size_t)0);
   char* w = (char*)ws;
   const size_t scan_bytes = plan_scan(N, p->n_samples).bytes;

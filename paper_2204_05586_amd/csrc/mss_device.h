@@ -30,6 +30,20 @@ struct FieldProgram {
   mss_term t[MSS_MAX_TERMS];
 };
 
+// Term sources for the interpreter: the kernel-argument program of a single
+// simulation, or a slice of a term table in device memory (batches).
+struct ArgTerms {
+  const FieldProgram& fp;
+  __device__ __forceinline__ int size() const { return fp.n_terms; }
+  __device__ __forceinline__ const mss_term& operator[](int i) const { return fp.t[i]; }
+};
+struct TableTerms {
+  const mss_term* __restrict__ t;
+  int n;
+  __device__ __forceinline__ int size() const { return n; }
+  __device__ __forceinline__ const mss_term& operator[](int i) const { return t[i]; }
+};
+
 template <int N>
 struct Mat {
   double r[N][N];
@@ -321,12 +335,14 @@ template <> struct Exponentiator<3> {
 // exactly as the plain definition t_k = t_start + k Dt,
 // tau_i = (l + c_i) dt, phase = 2 pi (f t) + phi prescribes.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void field_eval(const FieldProgram& fp, const double* __restrict__ params,
+template <class Terms>
+__device__ __forceinline__ void field_eval(const Terms& fp, const double* __restrict__ params,
                                            double t, double f[4]) {
 #pragma clang fp contract(off)
   double fx = 0.0, fy = 0.0, fz = 0.0, fq = 0.0;
-  for (int n = 0; n < fp.n_terms; ++n) {
-    const mss_term& tm = fp.t[n];
+  const int nt = fp.size();
+  for (int n = 0; n < nt; ++n) {
+    const mss_term& tm = fp[n];
     if (!(tm.t_on < t && t < tm.t_off)) continue;
     double amp = tm.a_slot >= 0 ? params[tm.a_slot] : tm.a;
     const double fr = tm.f_slot >= 0 ? params[tm.f_slot] : tm.f;
@@ -362,7 +378,8 @@ __device__ __forceinline__ void field_eval(const FieldProgram& fp, const double*
 
 // Angles theta_{1,2} = omega_bar_{1,2} dt of one CF4 fine step starting at
 // t_k + l dt, in the frame rotating at wr about z (wr = 0: lab frame).
-__device__ __forceinline__ void cf4_angles(const FieldProgram& fp, const double* __restrict__ params,
+template <class Terms>
+__device__ __forceinline__ void cf4_angles(const Terms& fp, const double* __restrict__ params,
                                            double tk, int l, double dt, double wr,
                                            double th1[4], double th2[4]) {
 #pragma clang fp contract(off)
@@ -393,7 +410,8 @@ __device__ __forceinline__ void cf4_angles(const FieldProgram& fp, const double*
 }
 
 // Start time of interval k and the frame rate omega_r = 2 pi f_z(t_k + Dt/2).
-__device__ __forceinline__ void interval_setup(const FieldProgram& fp, const double* __restrict__ params,
+template <class Terms>
+__device__ __forceinline__ void interval_setup(const Terms& fp, const double* __restrict__ params,
                                                double t_start, double Dt, int64_t k, int frame,
                                                double* tk_out, double* wr_out) {
 #pragma clang fp contract(off)
@@ -426,6 +444,40 @@ __device__ __forceinline__ void exit_frame(double wr, double Dt, Mat<N>& U) {
       U.i[a][b] = fma(c, xi, s * xr);
     }
   }
+}
+
+// Operator of one interval (rows a1-a9) computed by S = 2^sl cooperating
+// lanes: slice s integrates fine steps [s L / S, (s + 1) L / S) and the
+// partial products are combined in order with wave shuffles; the full
+// U_k (frame exit applied) ends up in the lane with s == 0.  Every lane of
+// the wave must call this (the shuffles need the whole wave).
+template <int N, class Terms>
+__device__ __forceinline__ void interval_operator(const Terms& terms, const double* __restrict__ params,
+                                                  double t_start, double Dt, double dt, int L,
+                                                  int tau, int frame, int64_t k, int s, int sl,
+                                                  bool active, Mat<N>& U, double* tk_out) {
+  set_identity<N>(U);
+  double tk = 0.0, wr = 0.0;
+  if (active) {
+    interval_setup(terms, params, t_start, Dt, k, frame, &tk, &wr);
+    const int l0 = (int)(((int64_t)s * L) >> sl);
+    const int l1 = (int)(((int64_t)(s + 1) * L) >> sl);
+    for (int l = l0; l < l1; ++l) {
+      double th1[4], th2[4];
+      cf4_angles(terms, params, tk, l, dt, wr, th1, th2);
+      Mat<N> E;
+      Exponentiator<N>::apply(th1, tau, E);
+      premultiply<N>(E, U);
+      Exponentiator<N>::apply(th2, tau, E);
+      premultiply<N>(E, U);
+    }
+  }
+  for (int d = 1; d < (1 << sl); d <<= 1) {
+    const Mat<N> o = shfl_down_mat<N>(U, d);
+    if ((s & (2 * d - 1)) == 0) premultiply<N>(o, U);
+  }
+  if (active && s == 0) exit_frame<N>(wr, Dt, U);
+  *tk_out = tk;
 }
 
 }  // namespace mss

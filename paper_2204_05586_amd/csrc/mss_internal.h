@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include "mss_device.h"
 
 namespace mss {
@@ -26,6 +28,16 @@ struct IntegrateArgs {
   int32_t frame;
   int32_t slices_log2;
 };
+
+// host helpers shared by the C-ABI translation units (mss_api.hip)
+mss_status api_fail(mss_status s, const char* fmt, ...);
+mss_status api_ok();
+mss_status api_hip_fail(hipError_t e, const char* what);
+std::string api_last_error_copy();
+mss_status api_validate_problem(const mss_problem* p);
+int api_device_cu_count();
+int api_plan_slices(int64_t K, int32_t L, int cu);
+int api_ilog2(int x);
 
 hipError_t launch_integrate(int N, const IntegrateArgs& a, int block, hipStream_t st);
 hipError_t launch_scan_reduce(int N, const double* M, int64_t n, double* agg, hipStream_t st);

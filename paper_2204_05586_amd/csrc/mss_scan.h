@@ -1,0 +1,129 @@
+// Tile routines of the ordered prefix product psi_{k+1} = U_k psi_k
+// (eq. integration_compilation): one wave owns a tile of kScanTile
+// consecutive N x N operators, each lane a run of kScanPerLane of them.
+#pragma once
+
+#include "mss_internal.h"
+
+namespace mss {
+
+// Product of the lane's (up to) kScanPerLane consecutive matrices, later on the left.
+template <int N>
+__device__ __forceinline__ void lane_product(const double* __restrict__ M, int64_t n, int64_t base,
+                                             Mat<N>& Q) {
+  set_identity<N>(Q);
+#pragma unroll
+  for (int e = 0; e < kScanPerLane; ++e) {
+    const int64_t idx = base + e;
+    if (idx < n) {
+      Mat<N> X;
+      load_mat<N>(M + (size_t)idx * 2 * N * N, X);
+      premultiply<N>(X, Q);
+    }
+  }
+}
+
+// Tile reduce: agg = M[tT + T - 1] ... M[tT] of tile t (T = kScanTile), one
+// wave per tile.  M points at element 0 of the sequence, n its length.
+template <int N>
+__device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_t n, int64_t tile,
+                                            int lane, double* __restrict__ agg_out) {
+  const int64_t base = tile * kScanTile + (int64_t)lane * kScanPerLane;
+  Mat<N> Q;
+  lane_product<N>(M, n, base, Q);
+  for (int d = 1; d < 64; d <<= 1) {
+    const Mat<N> o = shfl_down_mat<N>(Q, d);
+    if ((lane & (2 * d - 1)) == 0) premultiply<N>(o, Q);
+  }
+  if (lane == 0 && agg_out) store_mat<N>(agg_out, Q);
+}
+
+// Tile apply: before[i] = M[i-1] ... M[tT] start for i in tile t (the state
+// entering element i); after_last (optional) receives M[n-1] ... applied
+// when the tile holds the last element.  Every lane must call this.
+template <int N>
+__device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t n, int64_t tile,
+                                           int lane, bool valid, const double* __restrict__ start,
+                                           double* __restrict__ before,
+                                           double* __restrict__ after_last) {
+  const int64_t base = tile * kScanTile + (int64_t)lane * kScanPerLane;
+  Mat<N> P;
+  lane_product<N>(M, n, base, P);
+  // inclusive scan over lanes: P_lane = Q_lane ... Q_0
+  for (int d = 1; d < 64; d <<= 1) {
+    const Mat<N> o = shfl_up_mat<N>(P, d);
+    if (lane >= d) {
+      Mat<N> t;
+      matmul<N>(P, o, t);
+      P = t;
+    }
+  }
+  Mat<N> X = shfl_up_mat<N>(P, 1);
+  if (lane == 0) set_identity<N>(X);
+  if (!valid) return;
+  // v = X start
+  double vr[N], vi[N];
+  {
+    double sr[N], si[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      sr[a] = start[2 * a];
+      si[a] = start[2 * a + 1];
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        re = fma(X.r[a][b], sr[b], re);
+        re = fma(-X.i[a][b], si[b], re);
+        im = fma(X.r[a][b], si[b], im);
+        im = fma(X.i[a][b], sr[b], im);
+      }
+      vr[a] = re;
+      vi[a] = im;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kScanPerLane; ++e) {
+    const int64_t idx = base + e;
+    if (idx < n) {
+      double* o = before + (size_t)idx * 2 * N;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        o[2 * a] = vr[a];
+        o[2 * a + 1] = vi[a];
+      }
+      Mat<N> Y;
+      load_mat<N>(M + (size_t)idx * 2 * N * N, Y);
+      double wr_[N], wi_[N];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+          re = fma(Y.r[a][b], vr[b], re);
+          re = fma(-Y.i[a][b], vi[b], re);
+          im = fma(Y.r[a][b], vi[b], im);
+          im = fma(Y.i[a][b], vr[b], im);
+        }
+        wr_[a] = re;
+        wi_[a] = im;
+      }
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        vr[a] = wr_[a];
+        vi[a] = wi_[a];
+      }
+      if (idx == n - 1 && after_last) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          after_last[2 * a] = vr[a];
+          after_last[2 * a + 1] = vi[a];
+        }
+      }
+    }
+  }
+}
+
+}  // namespace mss

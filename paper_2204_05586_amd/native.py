@@ -25,7 +25,9 @@ MSS_OK, MSS_E_INVALID, MSS_E_NOMEM, MSS_E_DEVICE, MSS_E_UNSUPPORTED, MSS_E_BUSY,
 EXPORTS = [
     "mss_status_str", "mss_last_error", "mss_version", "mss_validate", "mss_plan_launch",
     "mss_workspace_size", "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
-    "mss_solve",
+    "mss_solve", "mss_batch_plan_create", "mss_batch_layout", "mss_batch_workspace_size",
+    "mss_batch_info", "mss_batch_run", "mss_batch_integrate", "mss_batch_propagate",
+    "mss_batch_plan_destroy",
 ]
 
 
@@ -59,6 +61,16 @@ class Launch(C.Structure):
     _fields_ = [("slices", C.c_int32), ("block", C.c_int32)]
 
 
+class BatchOptions(C.Structure):
+    _fields_ = [("slices_spin_half", C.c_int32), ("slices_spin_one", C.c_int32),
+                ("waves_per_simd", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("n_sims", C.c_int32), ("scan_levels", C.c_int32), ("grid_blocks", C.c_int32),
+                ("pad", C.c_int32), ("n_items", C.c_int64), ("total_samples", C.c_int64)]
+
+
 _lib = None
 
 
@@ -84,9 +96,22 @@ def lib() -> C.CDLL:
         L.mss_integrate.argtypes = [PP, vp, vp, vp, C.POINTER(Launch), vp]
         L.mss_propagate.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, vp, vp, sz, vp]
         L.mss_solve.argtypes = [PP, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        i64p = C.POINTER(C.c_int64)
+        L.mss_batch_plan_create.argtypes = [C.c_int32, PP, i64p, C.POINTER(BatchOptions),
+                                            C.POINTER(vp)]
+        L.mss_batch_layout.argtypes = [vp, i64p, i64p, i64p]
+        L.mss_batch_workspace_size.argtypes = [vp, C.c_int32, C.POINTER(sz)]
+        L.mss_batch_info.argtypes = [vp, C.POINTER(BatchInfo)]
+        L.mss_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_batch_integrate.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.mss_batch_propagate.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_batch_plan_destroy.argtypes = [vp]
+        L.mss_batch_plan_destroy.restype = None
         for name in ("mss_validate", "mss_plan_launch", "mss_workspace_size",
                      "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
-                     "mss_solve"):
+                     "mss_solve", "mss_batch_plan_create", "mss_batch_layout",
+                     "mss_batch_workspace_size", "mss_batch_info", "mss_batch_run",
+                     "mss_batch_integrate", "mss_batch_propagate"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -222,3 +247,114 @@ def solve(prob, store_u: bool = False, want_time: bool = False, device="cuda",
     ws = alloc_workspace(workspace_size(prob, store_u), device)
     solve_into(prob, params, psi0, psi, fin, U, time, ws, stream)
     return {"psi": psi, "psi_final": fin, "U": U, "time": time}
+
+
+# ---- batches ---------------------------------------------------------------
+
+class BatchPlan:
+    """A planned batch of simulations (mss_batch_plan_create).
+
+    The packed layout puts simulation i's initial/final state at
+    psi0_off[i], its states at state_off[i] and its operators at op_off[i]
+    (complex units).  Parameters are concatenated in simulation order."""
+
+    def __init__(self, problems, slices_spin_half=0, slices_spin_one=0, waves_per_simd=0,
+                 use_graph=False):
+        self.problems = list(problems)
+        n = len(self.problems)
+        self.packed = [PackedProblem(p) for p in self.problems]
+        arr = (Problem * max(1, n))()
+        for i, pk in enumerate(self.packed):
+            arr[i] = pk.c
+        self._arr = arr
+        counts = np.array([pk.n_params for pk in self.packed], dtype=np.int64)
+        self.param_off = np.zeros(max(1, n), dtype=np.int64)
+        if n:
+            self.param_off[:n] = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        self.n_params_total = int(counts.sum())
+        opt = BatchOptions(int(slices_spin_half), int(slices_spin_one), int(waves_per_simd),
+                           int(bool(use_graph)))
+        h = C.c_void_p()
+        check(lib().mss_batch_plan_create(
+            n, arr, self.param_off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(opt),
+            C.byref(h)))
+        self.handle = h
+        self.n = n
+        offs = [np.zeros(n + 1, dtype=np.int64) for _ in range(3)]
+        check(lib().mss_batch_layout(self.handle,
+                                     *[o.ctypes.data_as(C.POINTER(C.c_int64)) for o in offs]))
+        self.psi0_off, self.state_off, self.op_off = offs
+
+    def info(self) -> dict:
+        bi = BatchInfo()
+        check(lib().mss_batch_info(self.handle, C.byref(bi)))
+        return {"n_sims": bi.n_sims, "scan_levels": bi.scan_levels,
+                "grid_blocks": bi.grid_blocks, "n_items": bi.n_items,
+                "total_samples": bi.total_samples}
+
+    def workspace_size(self, store_u: bool) -> int:
+        n = C.c_size_t()
+        check(lib().mss_batch_workspace_size(self.handle, int(bool(store_u)), C.byref(n)))
+        return n.value
+
+    def params_host(self) -> np.ndarray:
+        parts = [np.asarray(p.params, dtype=np.float64).ravel() for p in self.problems]
+        return np.concatenate(parts) if self.n_params_total else np.zeros(0)
+
+    def psi0_host(self) -> np.ndarray:
+        return np.concatenate([np.asarray(p.psi0, dtype=np.complex128) for p in self.problems])
+
+    def allocate(self, store_u=False, device="cuda") -> dict:
+        import torch
+        params = self.params_host()
+        out = {
+            "params": torch.from_numpy(params).to(device) if params.size else None,
+            "psi0": torch.from_numpy(self.psi0_host()).to(device),
+            "psi": torch.empty(int(self.state_off[-1]), dtype=torch.complex128, device=device),
+            "psi_final": torch.empty(int(self.psi0_off[-1]), dtype=torch.complex128,
+                                     device=device),
+            "U": (torch.empty(int(self.op_off[-1]), dtype=torch.complex128, device=device)
+                  if store_u else None),
+        }
+        out["ws"] = alloc_workspace(self.workspace_size(store_u), device)
+        return out
+
+    def run(self, bufs: dict, stream=None) -> None:
+        ws = bufs["ws"]
+        check(lib().mss_batch_run(self.handle, _ptr(bufs["params"]), _ptr(bufs["psi0"]),
+                                  _ptr(bufs["psi"]), _ptr(bufs["psi_final"]), _ptr(bufs["U"]),
+                                  _ptr(ws), int(ws.numel()), _stream(stream)))
+
+    def integrate(self, bufs: dict, stream=None) -> None:
+        ws = bufs["ws"]
+        check(lib().mss_batch_integrate(self.handle, _ptr(bufs["params"]), _ptr(bufs["U"]),
+                                        _ptr(ws), int(ws.numel()), _stream(stream)))
+
+    def propagate(self, bufs: dict, stream=None) -> None:
+        ws = bufs["ws"]
+        check(lib().mss_batch_propagate(self.handle, _ptr(bufs["psi0"]), _ptr(bufs["psi"]),
+                                        _ptr(bufs["psi_final"]), _ptr(bufs["U"]), _ptr(ws),
+                                        int(ws.numel()), _stream(stream)))
+
+    def split(self, bufs: dict, i: int) -> dict:
+        """Views of simulation i's outputs: psi [K, N], psi_final [N], U [K, N, N]."""
+        p = self.problems[i]
+        K, N = int(p.n_samples), int(p.spin_twice) + 1
+        a, b = int(self.state_off[i]), int(self.state_off[i + 1])
+        out = {"psi": bufs["psi"][a:b].view(K, N),
+               "psi_final": bufs["psi_final"][int(self.psi0_off[i]):int(self.psi0_off[i + 1])]}
+        if bufs.get("U") is not None:
+            a, b = int(self.op_off[i]), int(self.op_off[i + 1])
+            out["U"] = bufs["U"][a:b].view(K, N, N)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mss_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
