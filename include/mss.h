@@ -241,6 +241,79 @@ mss_status mss_batch_propagate(mss_batch_plan* plan, const double* psi0, double*
 /* Free the plan (its graph, stream and descriptors). */
 void mss_batch_plan_destroy(mss_batch_plan* plan);
 
+/* ---- serving ------------------------------------------------------------
+ * Continuous batching of simulation requests (mixed spin and length) on the
+ * current device.  Requests are admitted in arrival order while their
+ * device block (K (N^2 + N) 16 bytes plus small state, parameter and scan
+ * arrays) fits in the HBM budget and an active slot is free; otherwise they
+ * wait (back-pressure).  A scheduler thread runs rounds: every active
+ * request gets a share of the round's work, all shares are integrated in
+ * one persistent launch, requests whose last share is in the round are
+ * scanned in it, and requests arriving meanwhile join the next round.
+ * Results stay in device memory until mss_server_release.  All calls are
+ * thread-safe. */
+typedef struct mss_server mss_server;
+
+typedef struct mss_server_options {
+  size_t hbm_budget;      /* bytes of device memory for requests (0: 80 % of free memory) */
+  int32_t max_active;     /* requests admitted at once (0: 512) */
+  int32_t slices;         /* lanes per interval, power of two <= 64 (0: 1) */
+  double iteration_steps; /* spin-1 fine steps per round (spin-1/2 steps weigh 1/16; 0: 3e7) */
+} mss_server_options;
+
+enum { MSS_REQ_QUEUED = 0, MSS_REQ_RUNNING = 1, MSS_REQ_DONE = 2, MSS_REQ_FAILED = 3 };
+
+typedef struct mss_request_info {
+  int32_t state;          /* MSS_REQ_* */
+  int32_t spin_twice;
+  int64_t n_samples;
+  const double* psi;      /* device [K][N] complex, valid when DONE until release */
+  const double* psi_final;/* device [N] */
+  const double* U;        /* device [K][N][N] */
+  double t_submit, t_admit, t_done; /* seconds on the server clock */
+} mss_request_info;
+
+typedef struct mss_server_stats {
+  int64_t submitted, completed, rounds;
+  int32_t queued, active;
+  double fine_steps;      /* fine steps integrated so far */
+  size_t bytes_in_use, bytes_peak, budget;
+} mss_server_stats;
+
+/* Reserve the budget on the current device and start the scheduler. */
+mss_status mss_server_create(const mss_server_options* options, mss_server** out);
+
+/* Queue a request.  problem, its terms, params (n_params doubles) and psi0
+ * (N complex) are HOST memory, copied before return.  MSS_E_NOMEM if the
+ * request can never fit in the budget. */
+mss_status mss_server_submit(mss_server* server, const mss_problem* problem, const double* params,
+                             const double* psi0, uint64_t* ticket);
+
+/* Current state of a request (never blocks). */
+mss_status mss_server_poll(mss_server* server, uint64_t ticket, mss_request_info* out);
+
+/* Block until the request is done (MSS_OK), failed (MSS_E_DEVICE) or the
+ * timeout passes (MSS_E_NOTREADY). */
+mss_status mss_server_wait(mss_server* server, uint64_t ticket, double timeout_s,
+                           mss_request_info* out);
+
+/* Device-to-device copy of a finished request's results into caller
+ * buffers (any may be NULL), enqueued on `stream`. */
+mss_status mss_server_copy_out(mss_server* server, uint64_t ticket, double* psi, double* psi_final,
+                               double* U, void* stream);
+
+/* Forget a request: a queued one is dropped, a finished one returns its
+ * device block to the pool; a running one gives MSS_E_BUSY. */
+mss_status mss_server_release(mss_server* server, uint64_t ticket);
+
+mss_status mss_server_stats_get(mss_server* server, mss_server_stats* out);
+
+/* Seconds since the server was created (the clock of the request times). */
+double mss_server_clock(const mss_server* server);
+
+/* Stop the scheduler after in-flight rounds and free everything. */
+void mss_server_destroy(mss_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,87 @@
+// Work sets: the descriptor format shared by the batched path and the
+// serving loop.  A work set is a list of sequences (simulations).  Each
+// sequence may ask for
+//   * integration of a range of its intervals [k_first, k_first + k_count)
+//     (interval operators U_k written at their global index k, node times
+//     from the global k, so a range gives exactly the operators the whole
+//     simulation would), and/or
+//   * the ordered product over all of its K_total operators (scan), writing
+//     its states and final state.
+// Descriptors carry absolute device pointers, so sequences may live in
+// unrelated allocations (one block per served request).
+#pragma once
+
+#include <vector>
+
+#include "mss_internal.h"
+
+namespace mss {
+
+struct SimDesc {
+  double t_start, dt_out, dt;
+  int64_t k_first;   // first interval integrated by this descriptor
+  int64_t k_count;   // intervals integrated (0: none)
+  int64_t K_total;   // length of the whole sequence (for the scan)
+  int64_t item_off;  // first integrator work item
+  const double* params;
+  const double* psi0;  // [N]
+  double* psi;         // [K_total][N]
+  double* psi_final;   // [N] or null
+  double* U;           // [K_total][N][N]
+  double* scan_ws;     // scan levels 1..top: per level [n_l][N][N] then [n_l][N]
+  int32_t spin_twice, n_terms, term_off, n_fine;
+  int32_t tau, frame, slices_log2, top;  // top: scan levels above 0; -1: no scan
+};
+
+// Scan geometry of a sequence of K operators: levels above 0 and the
+// scratch (bytes) of levels 1..top.
+int scan_top(int64_t K);
+size_t scan_scratch_bytes(int N, int64_t K);
+
+// Host-side builder: fills item offsets and the scan tile tables, then
+// packs everything for one upload.
+struct WorkSet {
+  std::vector<SimDesc> sims;
+  std::vector<mss_term> terms;
+  int64_t n_items = 0;
+  int n_levels = 0;                                  // max top over scanning sequences
+  std::vector<std::vector<int64_t>> reduce_tiles;    // [level][n + 1] prefix (levels 0..n_levels-1)
+  std::vector<std::vector<int64_t>> apply_tiles;     // [level][n + 1] prefix (levels 0..n_levels)
+
+  // Append a sequence; terms are copied unless identical to the previous
+  // sequence's list.  Pointers may be filled later (patch_pointers).
+  void add(const mss_problem& p, int slices_log2, int64_t k_first, int64_t k_count, bool scan);
+  // Compute item offsets and tile tables (call after the last add).
+  void finalize();
+  // Bytes of the packed descriptor image and the image itself.
+  size_t packed_bytes() const;
+  void pack(char* dst, size_t* o_sims, size_t* o_terms, std::vector<size_t>* o_reduce,
+            std::vector<size_t>* o_apply) const;
+
+ private:
+  const mss_term* last_terms_ = nullptr;
+  int last_n_terms_ = -1, last_term_off_ = -1;
+};
+
+// Device view of an uploaded work set.
+struct DevWork {
+  const SimDesc* sims = nullptr;
+  const mss_term* terms = nullptr;
+  std::vector<const int64_t*> reduce_tiles, apply_tiles;
+  std::vector<int64_t> reduce_total, apply_total;
+  int32_t n_sims = 0;
+  int64_t n_items = 0;
+  int n_levels = 0;
+};
+
+DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_t o_terms,
+                    const std::vector<size_t>& o_reduce, const std::vector<size_t>& o_apply);
+
+// Enqueue the integrator (counter cleared by a kernel first) over every
+// range of the work set; grid_blocks 256-thread workgroups.
+hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, int grid_blocks,
+                                 hipStream_t st);
+// Enqueue the scan of every scanning sequence (reduce up, apply down).
+hipError_t launch_work_scan(const DevWork& w, hipStream_t st);
+
+}  // namespace mss

@@ -1,0 +1,315 @@
+// Kernels and host builder of work sets (see mss_work.h).
+//
+// Integrator: persistent waves take work items (64 / S consecutive
+// intervals of one range, S lane-slices per interval) from an atomic
+// counter until it passes the item count, so every wave exits once the
+// queue is drained; no wave ever waits for another.
+// Scan: level by level; a wave locates its sequence by binary search over
+// the level's tile prefix and handles one tile of it.
+#include <string.h>
+
+#include <algorithm>
+
+#include "mss_scan.h"
+#include "mss_work.h"
+
+namespace mss {
+
+int scan_top(int64_t K) {
+  int top = 0;
+  int64_t n = K;
+  while (n > kScanTile) {
+    n = (n + kScanTile - 1) / kScanTile;
+    ++top;
+  }
+  return top;
+}
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t scan_scratch_bytes(int N, int64_t K) {
+  size_t b = 0;
+  int64_t n = K;
+  while (n > kScanTile) {
+    n = (n + kScanTile - 1) / kScanTile;
+    b += (size_t)n * (N * N + N) * 16;
+  }
+  return a256(b);
+}
+
+// ---------------------------------------------------------------------------
+// device
+// ---------------------------------------------------------------------------
+// largest i in [0, n) with prefix[i] <= x (non-decreasing prefix, prefix[0] = 0)
+__device__ __forceinline__ int find_segment(const int64_t* __restrict__ prefix, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t wave_broadcast(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+struct IntegrateWorkArgs {
+  const SimDesc* sims;
+  const mss_term* terms;
+  unsigned long long* counter;
+  int64_t n_items;
+  int32_t n_sims;
+};
+
+struct ScanWorkArgs {
+  const SimDesc* sims;
+  const int64_t* tiles;  // prefix over sequences at this level
+  int64_t n_tiles;
+  int32_t n_sims;
+  int32_t level;
+};
+
+__global__ void work_reset_kernel(unsigned long long* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
+}
+
+template <int N>
+__device__ __forceinline__ void work_item(const IntegrateWorkArgs& A, const SimDesc& s,
+                                          int64_t local, int lane) {
+  const int sl = s.slices_log2;
+  const int64_t j = local * (64 >> sl) + (lane >> sl);  // interval within the range
+  const int slice = lane & ((1 << sl) - 1);
+  const bool active = j < s.k_count;
+  const int64_t k = s.k_first + j;
+  Mat<N> U;
+  double tk;
+  interval_operator<N>(TableTerms{A.terms + s.term_off, s.n_terms}, s.params, s.t_start, s.dt_out,
+                       s.dt, s.n_fine, s.tau, s.frame, k, slice, sl, active, U, &tk);
+  if (active && slice == 0) store_mat<N>(s.U + (size_t)k * 2 * N * N, U);
+}
+
+__global__ void __launch_bounds__(256) work_integrate_kernel(const IntegrateWorkArgs A) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int64_t item = 0;
+    if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
+    item = wave_broadcast(item);
+    if (item >= A.n_items) break;
+    int lo = 0, hi = A.n_sims - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (A.sims[mid].item_off <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const SimDesc& s = A.sims[lo];
+    const int64_t local = item - s.item_off;
+    if (s.spin_twice == 2) work_item<3>(A, s, local, lane);
+    else work_item<2>(A, s, local, lane);
+  }
+}
+
+// Element count of a sequence at a scan level and the start of that level's
+// arrays in the sequence's scratch (levels >= 1).
+template <int N>
+__device__ __forceinline__ int64_t level_geometry(const SimDesc& s, int level, size_t* mats_off) {
+  int64_t n = s.K_total;
+  size_t off = 0;
+  for (int l = 1; l <= level; ++l) {
+    if (l > 1) off += (size_t)n * (N * N + N) * 2;
+    n = (n + kScanTile - 1) / kScanTile;
+  }
+  *mats_off = off;  // in doubles
+  return n;
+}
+
+template <int N>
+__device__ __forceinline__ void work_reduce_tile(const SimDesc& s, int level, int64_t local,
+                                                 int lane) {
+  size_t off = 0;
+  const int64_t n = level_geometry<N>(s, level, &off);
+  const double* M = level == 0 ? s.U : s.scan_ws + off;
+  size_t up_off = 0;
+  const int64_t n_up = level_geometry<N>(s, level + 1, &up_off);
+  (void)n_up;
+  double* out = s.scan_ws + up_off + (size_t)local * 2 * N * N;
+  tile_reduce<N>(M, n, local, lane, out);
+}
+
+template <int N>
+__device__ __forceinline__ void work_apply_tile(const SimDesc& s, int level, int64_t local,
+                                                int lane) {
+  size_t off = 0;
+  const int64_t n = level_geometry<N>(s, level, &off);
+  const double* M = level == 0 ? s.U : s.scan_ws + off;
+  double* before = level == 0 ? s.psi : s.scan_ws + off + (size_t)n * 2 * N * N;
+  const double* start;
+  if (level == s.top) {
+    start = s.psi0;
+  } else {
+    size_t up_off = 0;
+    const int64_t n_up = level_geometry<N>(s, level + 1, &up_off);
+    start = s.scan_ws + up_off + (size_t)n_up * 2 * N * N + (size_t)local * 2 * N;
+  }
+  tile_apply<N>(M, n, local, lane, true, start, before, level == 0 ? s.psi_final : nullptr);
+}
+
+__global__ void __launch_bounds__(256) work_reduce_kernel(const ScanWorkArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (tile >= A.n_tiles) return;  // the whole wave leaves together
+  const int i = find_segment(A.tiles, A.n_sims, tile);
+  const int64_t local = tile - A.tiles[i];
+  const SimDesc& s = A.sims[i];
+  if (s.spin_twice == 2) work_reduce_tile<3>(s, A.level, local, lane);
+  else work_reduce_tile<2>(s, A.level, local, lane);
+}
+
+__global__ void __launch_bounds__(256) work_apply_kernel(const ScanWorkArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (tile >= A.n_tiles) return;  // the whole wave leaves together
+  const int i = find_segment(A.tiles, A.n_sims, tile);
+  const int64_t local = tile - A.tiles[i];
+  const SimDesc& s = A.sims[i];
+  if (s.spin_twice == 2) work_apply_tile<3>(s, A.level, local, lane);
+  else work_apply_tile<2>(s, A.level, local, lane);
+}
+
+// ---------------------------------------------------------------------------
+// host
+// ---------------------------------------------------------------------------
+void WorkSet::add(const mss_problem& p, int slices_log2, int64_t k_first, int64_t k_count,
+                  bool scan) {
+  SimDesc d;
+  memset(&d, 0, sizeof d);
+  d.t_start = p.t_start;
+  d.dt_out = p.dt_out;
+  d.dt = p.dt_out / (double)p.n_fine;
+  d.k_first = k_first;
+  d.k_count = k_count;
+  d.K_total = p.n_samples;
+  d.spin_twice = p.spin_twice;
+  d.n_terms = p.n_terms;
+  d.n_fine = p.n_fine;
+  d.tau = p.spin_twice == 2 ? p.n_squares : 0;
+  d.frame = p.rotating_frame;
+  d.slices_log2 = slices_log2;
+  d.top = scan ? scan_top(p.n_samples) : -1;
+  if (last_terms_ && last_n_terms_ == p.n_terms &&
+      (p.n_terms == 0 || memcmp(last_terms_, p.terms, sizeof(mss_term) * p.n_terms) == 0)) {
+    d.term_off = last_term_off_;
+  } else {
+    d.term_off = (int32_t)terms.size();
+    for (int t = 0; t < p.n_terms; ++t) terms.push_back(p.terms[t]);
+    last_terms_ = p.terms;
+    last_n_terms_ = p.n_terms;
+    last_term_off_ = d.term_off;
+  }
+  sims.push_back(d);
+}
+
+void WorkSet::finalize() {
+  const int n = (int)sims.size();
+  int64_t item = 0;
+  n_levels = 0;
+  for (SimDesc& d : sims) {
+    d.item_off = item;
+    const int64_t per = 64 >> d.slices_log2;
+    item += (d.k_count + per - 1) / per;
+    n_levels = std::max(n_levels, d.top);
+  }
+  n_items = item;
+  reduce_tiles.assign(n_levels, std::vector<int64_t>(n + 1, 0));
+  apply_tiles.assign(n_levels + 1, std::vector<int64_t>(n + 1, 0));
+  for (int i = 0; i < n; ++i) {
+    const SimDesc& d = sims[i];
+    int64_t cnt = d.K_total;
+    for (int l = 0; l <= n_levels; ++l) {
+      const int64_t tiles = (cnt + kScanTile - 1) / kScanTile;
+      const bool scans = d.top >= 0;
+      if (l < n_levels) reduce_tiles[l][i + 1] = reduce_tiles[l][i] + (scans && l < d.top ? tiles : 0);
+      apply_tiles[l][i + 1] = apply_tiles[l][i] + (scans && l <= d.top ? tiles : 0);
+      cnt = tiles;
+    }
+  }
+}
+
+size_t WorkSet::packed_bytes() const {
+  size_t b = a256(sims.size() * sizeof(SimDesc)) + a256(std::max<size_t>(1, terms.size()) * sizeof(mss_term));
+  b += (reduce_tiles.size() + apply_tiles.size()) * a256((sims.size() + 1) * sizeof(int64_t));
+  return b;
+}
+
+void WorkSet::pack(char* dst, size_t* o_sims, size_t* o_terms, std::vector<size_t>* o_reduce,
+                   std::vector<size_t>* o_apply) const {
+  size_t off = 0;
+  *o_sims = off;
+  memcpy(dst + off, sims.data(), sims.size() * sizeof(SimDesc));
+  off += a256(sims.size() * sizeof(SimDesc));
+  *o_terms = off;
+  if (!terms.empty()) memcpy(dst + off, terms.data(), terms.size() * sizeof(mss_term));
+  off += a256(std::max<size_t>(1, terms.size()) * sizeof(mss_term));
+  const size_t tb = a256((sims.size() + 1) * sizeof(int64_t));
+  o_reduce->clear();
+  for (const auto& t : reduce_tiles) {
+    o_reduce->push_back(off);
+    memcpy(dst + off, t.data(), t.size() * sizeof(int64_t));
+    off += tb;
+  }
+  o_apply->clear();
+  for (const auto& t : apply_tiles) {
+    o_apply->push_back(off);
+    memcpy(dst + off, t.data(), t.size() * sizeof(int64_t));
+    off += tb;
+  }
+}
+
+DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_t o_terms,
+                    const std::vector<size_t>& o_reduce, const std::vector<size_t>& o_apply) {
+  DevWork d;
+  d.sims = (const SimDesc*)(dev_base + o_sims);
+  d.terms = (const mss_term*)(dev_base + o_terms);
+  d.n_sims = (int32_t)w.sims.size();
+  d.n_items = w.n_items;
+  d.n_levels = w.n_levels;
+  for (size_t l = 0; l < o_reduce.size(); ++l) {
+    d.reduce_tiles.push_back((const int64_t*)(dev_base + o_reduce[l]));
+    d.reduce_total.push_back(w.reduce_tiles[l].back());
+  }
+  for (size_t l = 0; l < o_apply.size(); ++l) {
+    d.apply_tiles.push_back((const int64_t*)(dev_base + o_apply[l]));
+    d.apply_total.push_back(w.apply_tiles[l].back());
+  }
+  return d;
+}
+
+hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, int grid_blocks,
+                                 hipStream_t st) {
+  if (w.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(work_reset_kernel, dim3(1), dim3(64), 0, st, counter);
+  IntegrateWorkArgs a{w.sims, w.terms, counter, w.n_items, w.n_sims};
+  hipLaunchKernelGGL(work_integrate_kernel, dim3(grid_blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_work_scan(const DevWork& w, hipStream_t st) {
+  for (int l = 0; l < w.n_levels; ++l) {
+    const int64_t tiles = w.reduce_total[l];
+    if (!tiles) continue;
+    ScanWorkArgs a{w.sims, w.reduce_tiles[l], tiles, w.n_sims, l};
+    hipLaunchKernelGGL(work_reduce_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, a);
+  }
+  for (int l = w.n_levels; l >= 0; --l) {
+    const int64_t tiles = w.apply_total[l];
+    if (!tiles) continue;
+    ScanWorkArgs a{w.sims, w.apply_tiles[l], tiles, w.n_sims, l};
+    hipLaunchKernelGGL(work_apply_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mss

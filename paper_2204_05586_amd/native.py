@@ -27,8 +27,12 @@ EXPORTS = [
     "mss_workspace_size", "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
     "mss_solve", "mss_batch_plan_create", "mss_batch_layout", "mss_batch_workspace_size",
     "mss_batch_info", "mss_batch_run", "mss_batch_integrate", "mss_batch_propagate",
-    "mss_batch_plan_destroy",
+    "mss_batch_plan_destroy", "mss_server_create", "mss_server_submit", "mss_server_poll",
+    "mss_server_wait", "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
+    "mss_server_clock", "mss_server_destroy",
 ]
+
+MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
 
 
 class MssError(RuntimeError):
@@ -64,6 +68,24 @@ class Launch(C.Structure):
 class BatchOptions(C.Structure):
     _fields_ = [("slices_spin_half", C.c_int32), ("slices_spin_one", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class ServerOptions(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("slices", C.c_int32),
+                ("iteration_steps", C.c_double)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("spin_twice", C.c_int32), ("n_samples", C.c_int64),
+                ("psi", C.c_void_p), ("psi_final", C.c_void_p), ("U", C.c_void_p),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rounds", C.c_int64),
+                ("queued", C.c_int32), ("active", C.c_int32), ("fine_steps", C.c_double),
+                ("bytes_in_use", C.c_size_t), ("bytes_peak", C.c_size_t),
+                ("budget", C.c_size_t)]
 
 
 class BatchInfo(C.Structure):
@@ -105,13 +127,26 @@ def lib() -> C.CDLL:
         L.mss_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.mss_batch_integrate.argtypes = [vp, vp, vp, vp, sz, vp]
         L.mss_batch_propagate.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(vp)]
+        L.mss_server_submit.argtypes = [vp, PP, vp, vp, C.POINTER(C.c_uint64)]
+        L.mss_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(RequestInfo)]
+        L.mss_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(RequestInfo)]
+        L.mss_server_copy_out.argtypes = [vp, C.c_uint64, vp, vp, vp, vp]
+        L.mss_server_release.argtypes = [vp, C.c_uint64]
+        L.mss_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+        L.mss_server_clock.argtypes = [vp]
+        L.mss_server_clock.restype = C.c_double
+        L.mss_server_destroy.argtypes = [vp]
+        L.mss_server_destroy.restype = None
         L.mss_batch_plan_destroy.argtypes = [vp]
         L.mss_batch_plan_destroy.restype = None
         for name in ("mss_validate", "mss_plan_launch", "mss_workspace_size",
                      "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
                      "mss_solve", "mss_batch_plan_create", "mss_batch_layout",
                      "mss_batch_workspace_size", "mss_batch_info", "mss_batch_run",
-                     "mss_batch_integrate", "mss_batch_propagate"):
+                     "mss_batch_integrate", "mss_batch_propagate", "mss_server_create",
+                     "mss_server_submit", "mss_server_poll", "mss_server_wait",
+                     "mss_server_copy_out", "mss_server_release", "mss_server_stats_get"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -351,6 +386,78 @@ class BatchPlan:
     def close(self):
         if getattr(self, "handle", None):
             lib().mss_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- serving ---------------------------------------------------------------
+
+class Server:
+    """Continuous-batching simulation server (mss_server_*)."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 0, slices: int = 0,
+                 iteration_steps: float = 0.0):
+        opt = ServerOptions(int(hbm_budget), int(max_active), int(slices),
+                            float(iteration_steps))
+        h = C.c_void_p()
+        check(lib().mss_server_create(C.byref(opt), C.byref(h)))
+        self.handle = h
+
+    def clock(self) -> float:
+        return lib().mss_server_clock(self.handle)
+
+    def submit(self, prob) -> int:
+        pk = PackedProblem(prob)
+        params = np.ascontiguousarray(np.asarray(prob.params, dtype=np.float64).ravel())
+        psi0 = np.ascontiguousarray(np.asarray(prob.psi0, dtype=np.complex128))
+        t = C.c_uint64()
+        check(lib().mss_server_submit(self.handle, pk.ref,
+                                      params.ctypes.data if params.size else None,
+                                      psi0.ctypes.data, C.byref(t)))
+        return t.value
+
+    @staticmethod
+    def _info(ri: RequestInfo) -> dict:
+        return {"state": ri.state, "spin_twice": ri.spin_twice, "n_samples": ri.n_samples,
+                "t_submit": ri.t_submit, "t_admit": ri.t_admit, "t_done": ri.t_done}
+
+    def poll(self, ticket: int) -> dict:
+        ri = RequestInfo()
+        check(lib().mss_server_poll(self.handle, ticket, C.byref(ri)))
+        return self._info(ri)
+
+    def wait(self, ticket: int, timeout: float = 60.0) -> dict:
+        ri = RequestInfo()
+        check(lib().mss_server_wait(self.handle, ticket, float(timeout), C.byref(ri)))
+        return self._info(ri)
+
+    def fetch(self, ticket: int, prob, want_u: bool = False, stream=None) -> dict:
+        """Copy a finished request's results into new device tensors."""
+        import torch
+        K, N = int(prob.n_samples), int(prob.spin_twice) + 1
+        psi = torch.empty((K, N), dtype=torch.complex128, device="cuda")
+        fin = torch.empty((N,), dtype=torch.complex128, device="cuda")
+        U = torch.empty((K, N, N), dtype=torch.complex128, device="cuda") if want_u else None
+        check(lib().mss_server_copy_out(self.handle, ticket, _ptr(psi), _ptr(fin), _ptr(U),
+                                        _stream(stream)))
+        return {"psi": psi, "psi_final": fin, "U": U}
+
+    def release(self, ticket: int) -> None:
+        check(lib().mss_server_release(self.handle, ticket))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(lib().mss_server_stats_get(self.handle, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mss_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
