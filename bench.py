@@ -160,6 +160,59 @@ def bench_batched(problems, steps: int, warmup: int, graph_reps: int) -> dict:
     return out
 
 
+def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib: float) -> dict:
+    """Poisson request streams (70 % spin-1, 30 % spin-1/2, K log-uniform in
+    [1e3, 1e6], 10 CF4 steps per interval) submitted at their arrival times
+    to one server; latency = completion - scheduled arrival."""
+    import queue
+    import threading
+    import numpy as np
+    from paper_2204_05586_amd import native, workloads as W
+    all_rates = [10.0, 30.0, 100.0, 300.0, 1000.0]
+    srv = native.Server(hbm_budget=int(budget_gib * (1 << 30)))
+    out = {}
+    for rate in rates:
+        n = int(min(max_requests, max(50, rate * seconds_per_rate)))
+        idx = all_rates.index(rate) if rate in all_rates else len(all_rates)
+        stream = W.serving_stream(rate, n_requests=n, rate_index=idx)
+        q, records = queue.Queue(), []
+
+        def collect():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                t, arrival, steps = item
+                info = srv.wait(t, 600.0)
+                records.append((arrival, info["t_submit"], info["t_done"], steps))
+                srv.release(t)
+
+        th = threading.Thread(target=collect)
+        th.start()
+        base = srv.clock() + 0.05
+        for r in stream:
+            delay = base + r.arrival - srv.clock()
+            if delay > 0:
+                time.sleep(delay)
+            q.put((srv.submit(r.problem), base + r.arrival, r.problem.fine_steps))
+        q.put(None)
+        th.join()
+        lat = np.array([d - a for a, _, d, _ in records]) * 1e3
+        lag = np.array([sub - a for a, sub, _, _ in records]) * 1e3
+        span = max(d for _, _, d, _ in records) - base
+        steps = sum(st for *_, st in records)
+        out[str(int(rate))] = {"requests": n, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                               "mean_ms": round(float(lat.mean()), 3),
+                               "submit_lag_p99_ms": round(float(np.percentile(lag, 99)), 3),
+                               "fine_steps_per_s": round(steps / span, 1)}
+    st = srv.stats()
+    out["server"] = {"rounds": st["rounds"], "bytes_peak": st["bytes_peak"],
+                     "budget": st["budget"]}
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +225,10 @@ def main():
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
                     help="target CPU seconds of the oracle sample (0: skip)")
+    ap.add_argument("--serve-rates", default="10,100,1000",
+                    help="request rates (req/s) of the serving sweep, '' to skip")
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="target stream length per rate (requests = rate x seconds, <= 2000)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -244,6 +301,11 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    serving = None
+    if args.serve_rates:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        serving = bench_serving(rates, args.serve_seconds, 2000, budget_gib=64.0)
+
     base = (cpu_baseline(base_problems, args.cpu_baseline_seconds)
             if args.cpu_baseline_seconds > 0 else None)
 
@@ -262,6 +324,7 @@ def main():
         "data": "synthetic",
         "config": config,
         **extra,
+        "latency": serving,
         "roofline": roofline,
         "cpu_baseline": base,
         "kernel_src": src_hash,
