@@ -73,9 +73,18 @@ enum { K_CONST = 0, K_COS = 1, K_SIN = 2, K_PWC = 3, K_PWC_COS = 4, K_PWC_SIN = 
 
 template <class R> using cx = std::complex<R>;
 
-template <class R> R two_pi() { return R(2) * std::acos(R(-1)); }
+using std::acos;
+using std::atan2;
+using std::cos;
+using std::floor;
+using std::hypot;
+using std::ldexp;
+using std::sin;
+using std::sqrt;
 
-template <class R> cx<R> expi(R x) { return cx<R>(std::cos(x), std::sin(x)); }
+template <class R> R two_pi() { return R(2) * acos(R(-1)); }
+
+template <class R> cx<R> expi(R x) { return cx<R>(cos(x), sin(x)); }
 
 // ---- field program ---------------------------------------------------------
 template <class R>
@@ -93,7 +102,7 @@ R phase(R f, R t, R phi) {
 template <class R>
 int64_t segment(const OTerm& tm, R t) {
   R x = (t - R(tm.seg_t0)) / R(tm.seg_len);
-  R fl = std::floor(x);
+  R fl = floor(x);
   int64_t s;
   if (fl < R(0)) s = 0;
   else if (fl > R(tm.n_seg - 1)) s = tm.n_seg - 1;
@@ -119,12 +128,62 @@ void field(const OProblem& p, const R* params, R t, R out[4]) {
     }
     switch (tm.kind) {
       case K_CONST: case K_PWC: v = amp; break;
-      case K_COS: case K_PWC_COS: v = amp * std::cos(phase(fr, t, ph)); break;
-      case K_SIN: case K_PWC_SIN: v = amp * std::sin(phase(fr, t, ph)); break;
+      case K_COS: case K_PWC_COS: v = amp * cos(phase(fr, t, ph)); break;
+      case K_SIN: case K_PWC_SIN: v = amp * sin(phase(fr, t, ph)); break;
       default: v = R(0); break;
     }
     out[tm.comp] = out[tm.comp] + v;
   }
+}
+
+// ---- forward-mode dual numbers --------------------------------------------
+// v + dx e_x + dy e_y with e_x e_x = e_x e_y = e_y e_y = 0: carried through the
+// exponentiators they give E together with dE/dtheta_x and dE/dtheta_y.
+template <class R>
+struct Dual {
+  R v, dx, dy;
+  Dual() : v(0), dx(0), dy(0) {}
+  Dual(R a) : v(a), dx(0), dy(0) {}
+  Dual(R a, R b, R c) : v(a), dx(b), dy(c) {}
+};
+template <class R> Dual<R> operator+(const Dual<R>& a, const Dual<R>& b) { return {a.v + b.v, a.dx + b.dx, a.dy + b.dy}; }
+template <class R> Dual<R> operator-(const Dual<R>& a, const Dual<R>& b) { return {a.v - b.v, a.dx - b.dx, a.dy - b.dy}; }
+template <class R> Dual<R> operator-(const Dual<R>& a) { return {-a.v, -a.dx, -a.dy}; }
+template <class R> Dual<R> operator*(const Dual<R>& a, const Dual<R>& b) {
+  return {a.v * b.v, a.dx * b.v + a.v * b.dx, a.dy * b.v + a.v * b.dy};
+}
+template <class R> Dual<R> operator/(const Dual<R>& a, const Dual<R>& b) {
+  const R q = a.v / b.v;
+  return {q, (a.dx - q * b.dx) / b.v, (a.dy - q * b.dy) / b.v};
+}
+template <class R> Dual<R>& operator+=(Dual<R>& a, const Dual<R>& b) { return a = a + b; }
+template <class R> Dual<R>& operator-=(Dual<R>& a, const Dual<R>& b) { return a = a - b; }
+template <class R> Dual<R>& operator*=(Dual<R>& a, const Dual<R>& b) { return a = a * b; }
+template <class R> Dual<R>& operator/=(Dual<R>& a, const Dual<R>& b) { return a = a / b; }
+template <class R> bool operator==(const Dual<R>& a, const Dual<R>& b) { return a.v == b.v; }
+template <class R> bool operator!=(const Dual<R>& a, const Dual<R>& b) { return a.v != b.v; }
+template <class R> Dual<R> cos(const Dual<R>& a) {
+  const R s = std::sin(a.v);
+  return {std::cos(a.v), -s * a.dx, -s * a.dy};
+}
+template <class R> Dual<R> sin(const Dual<R>& a) {
+  const R c = std::cos(a.v);
+  return {std::sin(a.v), c * a.dx, c * a.dy};
+}
+template <class R> Dual<R> sqrt(const Dual<R>& a) {
+  const R r = std::sqrt(a.v);
+  return {r, a.dx / (R(2) * r), a.dy / (R(2) * r)};
+}
+template <class R> Dual<R> hypot(const Dual<R>& x, const Dual<R>& y) {
+  const R h = std::hypot(x.v, y.v);
+  return {h, (x.v * x.dx + y.v * y.dx) / h, (x.v * x.dy + y.v * y.dy) / h};
+}
+template <class R> Dual<R> atan2(const Dual<R>& y, const Dual<R>& x) {
+  const R r2 = x.v * x.v + y.v * y.v;
+  return {std::atan2(y.v, x.v), (x.v * y.dx - y.v * x.dx) / r2, (x.v * y.dy - y.v * x.dy) / r2};
+}
+template <class R> Dual<R> ldexp(const Dual<R>& a, int e) {
+  return {std::ldexp(a.v, e), std::ldexp(a.dx, e), std::ldexp(a.dy, e)};
 }
 
 // ---- small dense complex matrices -----------------------------------------
@@ -155,10 +214,10 @@ Mat<R, N> matmul(const Mat<R, N>& A, const Mat<R, N>& B) {
 // Spin-1/2: exp(-i (theta_x J_x + theta_y J_y + theta_z J_z)), J = sigma / 2.
 template <class R>
 Mat<R, 2> exp_half(const R th[3]) {
-  R big = std::sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
+  R big = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
   if (big == R(0)) return Mat<R, 2>::identity();
-  R c = std::cos(big / R(2));
-  R s = std::sin(big / R(2)) / big;
+  R c = cos(big / R(2));
+  R s = sin(big / R(2)) / big;
   Mat<R, 2> e;
   e.m[0][0] = cx<R>(c, -s * th[2]);
   e.m[0][1] = cx<R>(-s * th[1], -s * th[0]);
@@ -170,23 +229,23 @@ Mat<R, 2> exp_half(const R th[3]) {
 // e^{i beta} - 1 without cancellation.
 template <class R>
 cx<R> expim1(R beta) {
-  R h = std::sin(beta / R(2));
-  return cx<R>(R(-2) * h * h, std::sin(beta));
+  R h = sin(beta / R(2));
+  return cx<R>(R(-2) * h * h, sin(beta));
 }
 
 // Residual a = T - I of the symmetric Lie-Trotter factor for the step angles
 // theta = (theta_x, theta_y, theta_z, theta_q) and n = 2^tau.
 template <class R>
 Mat<R, 3> lie_trotter_residual(const R th[4], int tau) {
-  const R n = std::ldexp(R(1), tau);
+  const R n = ldexp(R(1), tau);
   const R z = th[2] / n;
   const R q = th[3] / n;
-  const R Phi = std::hypot(th[0], th[1]) / n;
-  const R phi = std::atan2(th[1], th[0]);
-  const R C = std::cos(Phi / R(2));
-  const R S = std::sin(Phi / R(2));
-  const R sPhi = std::sin(Phi);
-  const R r = R(1) / std::sqrt(R(2));
+  const R Phi = hypot(th[0], th[1]) / n;
+  const R phi = atan2(th[1], th[0]);
+  const R C = cos(Phi / R(2));
+  const R S = sin(Phi / R(2));
+  const R sPhi = sin(Phi);
+  const R r = R(1) / sqrt(R(2));
   (void)C;
   const cx<R> mi(R(0), R(-1));
   const cx<R> off = mi * cx<R>(r * sPhi, R(0));  // (-i / sqrt 2) sin(Phi)
@@ -242,7 +301,7 @@ template <class R> R mval(int N, int i) { return N == 2 ? (i == 0 ? R(0.5) : R(-
 // ---- one output interval -----------------------------------------------------
 template <class R, int N>
 Mat<R, N> interval_operator(const OProblem& p, const R* params, int64_t k) {
-  const R sq3 = std::sqrt(R(3));
+  const R sq3 = sqrt(R(3));
   const R c1 = (R(1) - R(1) / sq3) / R(2);
   const R c2 = (R(1) + R(1) / sq3) / R(2);
   const R wp = (R(3) + R(2) * sq3) / R(12);
@@ -362,6 +421,209 @@ int solve(const OProblem* p, const R* params, const R* psi0, R* U, R* psi, R* ps
   return 0;
 }
 
+
+// ---- adjoint: gradient of a final-state population -------------------------
+// loss = |psi_final[m]|^2 is differentiated through the same discrete map:
+// the costate lambda_final = e_m psi_final[m] (so that dloss = 2 Re lambda^H
+// dpsi_final) is pulled back through every operator (lambda_k = U_k^H
+// lambda_{k+1}); inside an interval each exponential E contributes
+// dloss/dtheta_a = 2 Re(lambda_after^H dE/dtheta_a psi_before), with dE from
+// the dual-number exponentiator; the chain rule then runs through the CF4
+// weights, the frame rotation of the transverse field and the field terms.
+// Gradients exist for parameters used by x and y terms.
+
+template <int N>
+void exp_tangents(const double th[4], int tau, Mat<double, N>& E, Mat<double, N>& Ex,
+                  Mat<double, N>& Ey) {
+  Dual<double> t[4] = {Dual<double>(th[0], 1, 0), Dual<double>(th[1], 0, 1), Dual<double>(th[2]),
+                       Dual<double>(th[3])};
+  Mat<Dual<double>, N> M = Exp<Dual<double>, N>::apply(t, tau);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const cx<Dual<double>>& z = M.m[i][j];
+      E.m[i][j] = cx<double>(z.real().v, z.imag().v);
+      Ex.m[i][j] = cx<double>(z.real().dx, z.imag().dx);
+      Ey.m[i][j] = cx<double>(z.real().dy, z.imag().dy);
+    }
+}
+
+template <int N>
+void matvec(const Mat<double, N>& A, const cx<double>* x, cx<double>* y) {
+  for (int i = 0; i < N; ++i) {
+    cx<double> s(0, 0);
+    for (int j = 0; j < N; ++j) s += A.m[i][j] * x[j];
+    y[i] = s;
+  }
+}
+
+template <int N>
+void matvec_h(const Mat<double, N>& A, const cx<double>* x, cx<double>* y) {  // A^H x
+  for (int i = 0; i < N; ++i) {
+    cx<double> s(0, 0);
+    for (int j = 0; j < N; ++j) s += std::conj(A.m[j][i]) * x[j];
+    y[i] = s;
+  }
+}
+
+// 2 Re(l^H A x)
+template <int N>
+double bilinear(const cx<double>* l, const Mat<double, N>& A, const cx<double>* x) {
+  cx<double> Ax[N];
+  matvec<N>(A, x, Ax);
+  cx<double> s(0, 0);
+  for (int i = 0; i < N; ++i) s += std::conj(l[i]) * Ax[i];
+  return 2.0 * s.real();
+}
+
+// d field-term value / d parameter slots at time t, scaled by G = dloss/df.
+void field_param_grad(const OProblem& p, const double* params, double t, double Gx, double Gy,
+                      double* grad) {
+  for (int i = 0; i < p.n_terms; ++i) {
+    const OTerm& tm = p.terms[i];
+    if (tm.comp > 1) continue;
+    if (!(tm.t_on < t && t < tm.t_off)) continue;
+    const double G = tm.comp == 0 ? Gx : Gy;
+    int a_slot = tm.a_slot, phi_slot = tm.phi_slot;
+    double amp = param_or(params, tm.a_slot, tm.a);
+    double ph = param_or(params, tm.phi_slot, tm.phi);
+    const double fr = param_or(params, tm.f_slot, tm.f);
+    if (tm.kind == K_PWC || tm.kind == K_PWC_COS || tm.kind == K_PWC_SIN) {
+      const int64_t s = segment(tm, t);
+      if (tm.seg_a_slot >= 0) {
+        a_slot = (int)(tm.seg_a_slot + s);
+        amp = params[a_slot];
+      }
+      if (tm.seg_phi_slot >= 0) {
+        phi_slot = (int)(tm.seg_phi_slot + s);
+        ph = params[phi_slot];
+      }
+    }
+    if (tm.kind == K_CONST || tm.kind == K_PWC) {
+      if (a_slot >= 0) grad[a_slot] += G;
+      continue;
+    }
+    const double arg = phase(fr, t, ph);
+    const bool is_cos = tm.kind == K_COS || tm.kind == K_PWC_COS;
+    const double val = is_cos ? cos(arg) : sin(arg);       // d value / d amp
+    const double dar = is_cos ? -amp * sin(arg) : amp * cos(arg);  // d value / d arg
+    if (a_slot >= 0) grad[a_slot] += G * val;
+    if (phi_slot >= 0) grad[phi_slot] += G * dar;
+    if (tm.f_slot >= 0) grad[tm.f_slot] += G * dar * two_pi<double>() * t;
+  }
+}
+
+template <int N>
+void interval_adjoint(const OProblem& p, const double* params, int64_t k, const cx<double>* psi_k,
+                      const cx<double>* lam_next, double* grad) {
+  const double sq3 = sqrt(3.0);
+  const double c1 = (1.0 - 1.0 / sq3) / 2.0;
+  const double c2 = (1.0 + 1.0 / sq3) / 2.0;
+  const double wp = (3.0 + 2.0 * sq3) / 12.0;
+  const double wm = (3.0 - 2.0 * sq3) / 12.0;
+  const double Dt = p.dt_out;
+  const double dt = Dt / (double)p.n_fine;
+  const double tk = p.t_start + (double)k * Dt;
+  double wr = 0.0;
+  if (p.rotating_frame) {
+    double f[4];
+    field<double>(p, params, tk + Dt / 2.0, f);
+    wr = two_pi<double>() * f[2];
+  }
+  struct Step {
+    double tau[2];
+    Mat<double, N> E[2], Ex[2], Ey[2];
+    cx<double> before[2][N];
+  };
+  std::vector<Step> steps(p.n_fine);
+  cx<double> v[N];
+  for (int i = 0; i < N; ++i) v[i] = psi_k[i];
+  const double cnode[2] = {c1, c2};
+  for (int l = 0; l < p.n_fine; ++l) {
+    Step& st = steps[l];
+    double w[2][4];
+    for (int i = 0; i < 2; ++i) {
+      const double tau_i = ((double)l + cnode[i]) * dt;
+      st.tau[i] = tau_i;
+      double f[4];
+      field<double>(p, params, tk + tau_i, f);
+      for (int j = 0; j < 4; ++j) w[i][j] = two_pi<double>() * f[j];
+      cx<double> xy = cx<double>(w[i][0], w[i][1]) * expi(-(wr * tau_i));
+      w[i][0] = xy.real();
+      w[i][1] = xy.imag();
+      w[i][2] = w[i][2] - wr;
+    }
+    double th[2][4];
+    for (int j = 0; j < 4; ++j) {
+      th[0][j] = (wp * w[0][j] + wm * w[1][j]) * dt;
+      th[1][j] = (wm * w[0][j] + wp * w[1][j]) * dt;
+    }
+    for (int e = 0; e < 2; ++e) {
+      exp_tangents<N>(th[e], p.n_squares, st.E[e], st.Ex[e], st.Ey[e]);
+      for (int i = 0; i < N; ++i) st.before[e][i] = v[i];
+      cx<double> nv[N];
+      matvec<N>(st.E[e], v, nv);
+      for (int i = 0; i < N; ++i) v[i] = nv[i];
+    }
+  }
+  // costate at the end of the interval in frame coordinates: R^H lambda_{k+1}
+  cx<double> lam[N];
+  for (int i = 0; i < N; ++i) lam[i] = expi(mval<double>(N, i) * (wr * Dt)) * lam_next[i];
+  for (int l = p.n_fine - 1; l >= 0; --l) {
+    Step& st = steps[l];
+    double gx[2], gy[2];
+    for (int e = 1; e >= 0; --e) {
+      gx[e] = bilinear<N>(lam, st.Ex[e], st.before[e]);
+      gy[e] = bilinear<N>(lam, st.Ey[e], st.before[e]);
+      cx<double> nl[N];
+      matvec_h<N>(st.E[e], lam, nl);
+      for (int i = 0; i < N; ++i) lam[i] = nl[i];
+    }
+    // dloss / d omega'_{x,y} at the two nodes
+    const double Gp[2][2] = {{dt * (wp * gx[0] + wm * gx[1]), dt * (wp * gy[0] + wm * gy[1])},
+                             {dt * (wm * gx[0] + wp * gx[1]), dt * (wm * gy[0] + wp * gy[1])}};
+    for (int i = 0; i < 2; ++i) {
+      const double a = wr * st.tau[i];
+      const double c = cos(a), s = sin(a);
+      const double gwx = Gp[i][0] * c - Gp[i][1] * s;
+      const double gwy = Gp[i][0] * s + Gp[i][1] * c;
+      field_param_grad(p, params, tk + st.tau[i], two_pi<double>() * gwx,
+                       two_pi<double>() * gwy, grad);
+    }
+  }
+}
+
+template <int N>
+int adjoint_population(const OProblem& p, const double* params, const double* psi0, int m,
+                       double* loss, double* grad) {
+  const int64_t K = p.n_samples;
+  const int P = p.n_params;
+  std::vector<double> Ub((size_t)K * 2 * N * N);
+  operators<double, N>(p, params, 0, K, Ub.data());
+  std::vector<double> psib((size_t)K * 2 * N);
+  double fin[2 * N];
+  states<double, N>(K, Ub.data(), psi0, psib.data(), fin);
+  *loss = fin[2 * m] * fin[2 * m] + fin[2 * m + 1] * fin[2 * m + 1];
+  std::vector<cx<double>> lam((size_t)(K + 1) * N, cx<double>(0, 0));
+  lam[(size_t)K * N + m] = cx<double>(fin[2 * m], fin[2 * m + 1]);
+  for (int64_t k = K - 1; k >= 0; --k) {
+    Mat<double, N> Uk = load<double, N>(Ub.data() + (size_t)k * 2 * N * N);
+    matvec_h<N>(Uk, &lam[(size_t)(k + 1) * N], &lam[(size_t)k * N]);
+  }
+  std::vector<double> part((size_t)K * P, 0.0);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t k = 0; k < K; ++k) {
+    cx<double> pk[N];
+    for (int i = 0; i < N; ++i) pk[i] = cx<double>(psib[(size_t)(k * N + i) * 2], psib[(size_t)(k * N + i) * 2 + 1]);
+    interval_adjoint<N>(p, params, k, pk, &lam[(size_t)(k + 1) * N], &part[(size_t)k * P]);
+  }
+  for (int q = 0; q < P; ++q) {
+    double s = 0.0;
+    for (int64_t k = 0; k < K; ++k) s += part[(size_t)k * P + q];
+    grad[q] = s;
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -400,6 +662,22 @@ int oracle_states(int spin_twice, int64_t K, const double* U, const double* psi0
   else if (spin_twice == 2) states<double, 3>(K, U, psi0, psi, psi_final);
   else return 1;
   return 0;
+}
+
+// loss = |psi_final[m]|^2 and grad[q] = dloss/dparams[q] for q < n_params.
+// Returns 1 on bad arguments, 2 if a z or q term uses a parameter slot.
+int oracle_adjoint_population(const OProblem* p, const double* params, const double* psi0, int m,
+                              double* loss, double* grad) {
+  if (!p || p->n_samples < 1 || p->n_fine < 1 || m < 0 || m > p->spin_twice) return 1;
+  for (int i = 0; i < p->n_terms; ++i) {
+    const OTerm& t = p->terms[i];
+    const bool slots = t.a_slot >= 0 || t.f_slot >= 0 || t.phi_slot >= 0 || t.seg_a_slot >= 0 ||
+                       t.seg_phi_slot >= 0;
+    if (slots && t.comp > 1) return 2;
+  }
+  if (p->spin_twice == 1) return adjoint_population<2>(*p, params, psi0, m, loss, grad);
+  if (p->spin_twice == 2) return adjoint_population<3>(*p, params, psi0, m, loss, grad);
+  return 1;
 }
 
 int oracle_solve(const OProblem* p, const double* params, const double* psi0, double* U,

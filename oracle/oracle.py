@@ -75,6 +75,8 @@ def lib():
         L.oracle_states.restype = C.c_int
         L.oracle_solve.argtypes = [C.POINTER(_Problem), dp, dp, dp, dp, dp]
         L.oracle_solve.restype = C.c_int
+        L.oracle_adjoint_population.argtypes = [C.POINTER(_Problem), dp, dp, C.c_int, dp, dp]
+        L.oracle_adjoint_population.restype = C.c_int
         ldp = C.c_void_p
         L.oracle_solve_ld.argtypes = [C.POINTER(_Problem), ldp, ldp, ldp]
         L.oracle_solve_ld.restype = C.c_int
@@ -209,3 +211,25 @@ def final_state_ld(prob, params_ld: np.ndarray | None = None) -> np.ndarray:
     if rc:
         raise ValueError("oracle_solve_ld: bad arguments")
     return out
+
+
+def adjoint_population(prob, m: int) -> tuple[float, np.ndarray]:
+    """loss = |psi_final[m]|^2 and its gradient w.r.t. every parameter slot
+    (reverse mode through the same discrete map)."""
+    pk = _Packed(prob)
+    v0 = np.ascontiguousarray(np.asarray(prob.psi0, dtype=np.complex128))
+    loss = np.zeros(1)
+    grad = np.zeros(max(1, pk.p.n_params))
+    rc = lib().oracle_adjoint_population(C.byref(pk.p), _dp(pk.params), _dp(v0.view(np.float64)),
+                                         int(m), _dp(loss), _dp(grad))
+    if rc == 2:
+        raise ValueError("gradients need parameter slots on x and y terms only")
+    if rc:
+        raise ValueError("oracle_adjoint_population: bad arguments")
+    return float(loss[0]), grad[:pk.p.n_params].copy()
+
+
+def population_ld(prob, m: int, params_ld: np.ndarray) -> np.longdouble:
+    """|psi_final[m]|^2 in extended precision at the given parameters."""
+    out = final_state_ld(prob, params_ld)
+    return out[m, 0] * out[m, 0] + out[m, 1] * out[m, 1]
