@@ -314,6 +314,34 @@ double mss_server_clock(const mss_server* server);
 /* Stop the scheduler after in-flight rounds and free everything. */
 void mss_server_destroy(mss_server* server);
 
+/* ---- adjoint ------------------------------------------------------------
+ * Gradients of final-state populations with respect to field parameters,
+ * for a batch of simulations: loss_i = |psi_final_i[m]|^2 and
+ * grad[param_off[i] + p] = d loss_i / d params[param_off[i] + p].  A
+ * discrete adjoint of the whole path (derivatives of the computed CF4
+ * steps, exponentiators included, through the frame and field terms).
+ * Interval boundaries are the checkpoints: forward states and costates are
+ * kept per interval and each interval's fine steps are replayed backward.
+ * Parameters may be used by x and y terms (any kind, at most 4
+ * parameterised terms per simulation); a z or q term with a parameter slot
+ * gives MSS_E_UNSUPPORTED.  Gradients are summed with FP64 atomics, so
+ * their last bits may vary between runs. */
+typedef struct mss_adjoint_plan mss_adjoint_plan;
+
+/* Validate and plan (host arrays of n problems / parameter offsets); the
+ * packed layout of psi0 / psi_final is that of mss_batch_layout. */
+mss_status mss_adjoint_plan_create(int32_t n, const mss_problem* problems, const int64_t* param_off,
+                                   int32_t level_m, mss_adjoint_plan** out);
+mss_status mss_adjoint_workspace_size(const mss_adjoint_plan* plan, size_t* bytes);
+/* Length of the gradient array: max over i of param_off[i] + n_params_i. */
+mss_status mss_adjoint_param_count(const mss_adjoint_plan* plan, int64_t* count);
+/* loss: device [n]; grad: device [param count] (overwritten); psi_final:
+ * optional device copy of the final states.  Asynchronous on `stream`. */
+mss_status mss_adjoint_run(mss_adjoint_plan* plan, const double* params, const double* psi0,
+                           double* loss, double* grad, double* psi_final, void* ws,
+                           size_t ws_bytes, void* stream);
+void mss_adjoint_plan_destroy(mss_adjoint_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,9 @@ EXPORTS = [
     "mss_batch_info", "mss_batch_run", "mss_batch_integrate", "mss_batch_propagate",
     "mss_batch_plan_destroy", "mss_server_create", "mss_server_submit", "mss_server_poll",
     "mss_server_wait", "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
-    "mss_server_clock", "mss_server_destroy",
+    "mss_server_clock", "mss_server_destroy", "mss_adjoint_plan_create",
+    "mss_adjoint_workspace_size", "mss_adjoint_param_count", "mss_adjoint_run",
+    "mss_adjoint_plan_destroy",
 ]
 
 MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
@@ -138,6 +140,12 @@ def lib() -> C.CDLL:
         L.mss_server_clock.restype = C.c_double
         L.mss_server_destroy.argtypes = [vp]
         L.mss_server_destroy.restype = None
+        L.mss_adjoint_plan_create.argtypes = [C.c_int32, PP, i64p, C.c_int32, C.POINTER(vp)]
+        L.mss_adjoint_workspace_size.argtypes = [vp, C.POINTER(sz)]
+        L.mss_adjoint_param_count.argtypes = [vp, i64p]
+        L.mss_adjoint_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_adjoint_plan_destroy.argtypes = [vp]
+        L.mss_adjoint_plan_destroy.restype = None
         L.mss_batch_plan_destroy.argtypes = [vp]
         L.mss_batch_plan_destroy.restype = None
         for name in ("mss_validate", "mss_plan_launch", "mss_workspace_size",
@@ -146,7 +154,9 @@ def lib() -> C.CDLL:
                      "mss_batch_workspace_size", "mss_batch_info", "mss_batch_run",
                      "mss_batch_integrate", "mss_batch_propagate", "mss_server_create",
                      "mss_server_submit", "mss_server_poll", "mss_server_wait",
-                     "mss_server_copy_out", "mss_server_release", "mss_server_stats_get"):
+                     "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
+                     "mss_adjoint_plan_create", "mss_adjoint_workspace_size",
+                     "mss_adjoint_param_count", "mss_adjoint_run"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -458,6 +468,71 @@ class Server:
     def close(self):
         if getattr(self, "handle", None):
             lib().mss_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- adjoint ---------------------------------------------------------------
+
+class AdjointPlan:
+    """Gradients of |psi_final[m]|^2 w.r.t. field parameters (mss_adjoint_*)."""
+
+    def __init__(self, problems, level_m: int):
+        self.problems = list(problems)
+        n = len(self.problems)
+        self.packed = [PackedProblem(p) for p in self.problems]
+        arr = (Problem * max(1, n))()
+        for i, pk in enumerate(self.packed):
+            arr[i] = pk.c
+        self._arr = arr
+        counts = np.array([pk.n_params for pk in self.packed], dtype=np.int64)
+        self.param_off = np.zeros(max(1, n), dtype=np.int64)
+        if n:
+            self.param_off[:n] = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        h = C.c_void_p()
+        check(lib().mss_adjoint_plan_create(
+            n, arr, self.param_off.ctypes.data_as(C.POINTER(C.c_int64)), int(level_m),
+            C.byref(h)))
+        self.handle = h
+        self.n = n
+        cnt = C.c_int64()
+        check(lib().mss_adjoint_param_count(self.handle, C.byref(cnt)))
+        self.n_grad = cnt.value
+        nb = C.c_size_t()
+        check(lib().mss_adjoint_workspace_size(self.handle, C.byref(nb)))
+        self.ws_bytes = nb.value
+
+    def allocate(self, device="cuda") -> dict:
+        import torch
+        params = np.concatenate([np.asarray(p.params, dtype=np.float64).ravel()
+                                 for p in self.problems]) if self.n_grad else np.zeros(0)
+        psi0 = np.concatenate([np.asarray(p.psi0, dtype=np.complex128) for p in self.problems])
+        return {"params": torch.from_numpy(params).to(device) if params.size else None,
+                "psi0": torch.from_numpy(psi0).to(device),
+                "loss": torch.empty(self.n, dtype=torch.float64, device=device),
+                "grad": torch.empty(max(1, self.n_grad), dtype=torch.float64, device=device),
+                "psi_final": torch.empty(psi0.size, dtype=torch.complex128, device=device),
+                "ws": alloc_workspace(self.ws_bytes, device)}
+
+    def run(self, bufs: dict, stream=None) -> None:
+        ws = bufs["ws"]
+        check(lib().mss_adjoint_run(self.handle, _ptr(bufs["params"]), _ptr(bufs["psi0"]),
+                                    _ptr(bufs["loss"]), _ptr(bufs["grad"]),
+                                    _ptr(bufs.get("psi_final")), _ptr(ws), int(ws.numel()),
+                                    _stream(stream)))
+
+    def grad_of(self, bufs: dict, i: int):
+        a = int(self.param_off[i])
+        return bufs["grad"][a:a + self.packed[i].n_params]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mss_adjoint_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

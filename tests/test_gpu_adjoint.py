@@ -1,0 +1,82 @@
+"""GPU adjoint (gradients of a final population w.r.t. field parameters)
+against the oracle's adjoint and extended-precision central differences."""
+import numpy as np
+import pytest
+
+from paper_2204_05586_amd import workloads as W
+from tests.test_oracle_adjoint import _control_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gpu_adjoint(probs, m):
+    import torch
+    from paper_2204_05586_amd import native
+    plan = native.AdjointPlan(probs, m)
+    bufs = plan.allocate()
+    print(f"[gpu] adjoint n={len(probs)} grads={plan.n_grad} ws={plan.ws_bytes}", flush=True)
+    plan.run(bufs)
+    torch.cuda.synchronize()
+    out = {"loss": bufs["loss"].cpu().numpy(),
+           "grad": [plan.grad_of(bufs, i).cpu().numpy() for i in range(len(probs))],
+           "psi_final": bufs["psi_final"].cpu().numpy()}
+    plan.close()
+    return out
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_adjoint_matches_oracle_small(torch_dev, oracle):
+    """Mixed spins, frame on/off, all term kinds with slots."""
+    cs, pw = ("cos", "sin"), ("pwc",)
+    probs = [_control_problem(2, frame=True, seed=1, extra=cs),
+             _control_problem(2, frame=False, seed=2, extra=pw),
+             _control_problem(1, frame=True, seed=3, extra=cs),
+             _control_problem(1, frame=False, seed=4, extra=pw),
+             _control_problem(2, frame=True, seed=5, K=301, L=3, extra=cs)]
+    m = 1
+    g = _gpu_adjoint(probs, m)
+    for i, p in enumerate(probs):
+        loss, grad = oracle.adjoint_population(p, m)
+        assert abs(g["loss"][i] - loss) < 1e-12, (i, g["loss"][i], loss)
+        r = _rel(g["grad"][i], grad)
+        print(f"adjoint {i}: loss {loss:.6f} rel grad err {r:.2e}", flush=True)
+        assert r <= 1e-9, (i, r)
+
+
+def test_adjoint_control_workload_subset(torch_dev, oracle):
+    """Full-size control instances (256 segments x (amplitude, phase), 1 ms,
+    1e5 CF4 steps, tau = 28): GPU vs oracle adjoint on every gradient
+    entry, and vs extended-precision central differences (h = 1e-6) on a
+    seeded subset of the controls."""
+    probs = W.control_batch(n_inst=4)
+    m = 1
+    g = _gpu_adjoint(probs, m)
+    for i in (0, 3):
+        loss, grad = oracle.adjoint_population(probs[i], m)
+        assert abs(g["loss"][i] - loss) < 1e-11
+        r = _rel(g["grad"][i], grad)
+        print(f"control {i}: loss {loss:.6f} rel grad err vs oracle adjoint {r:.2e}", flush=True)
+        assert r <= 1e-9
+    rng = np.random.default_rng(44)
+    p = probs[0]
+    par = np.asarray(p.params, dtype=np.longdouble)
+    for q in rng.choice(par.size, 4, replace=False):
+        h = np.longdouble(1e-6) * max(np.longdouble(1.0), abs(par[q]))
+        pp, pm = par.copy(), par.copy()
+        pp[q] += h
+        pm[q] -= h
+        fd = float((oracle.population_ld(p, m, pp) - oracle.population_ld(p, m, pm)) / (2 * h))
+        scale = np.max(np.abs(g["grad"][0]))
+        print(f"control 0 slot {q}: adjoint {g['grad'][0][q]:.10e} fd {fd:.10e}", flush=True)
+        assert abs(g["grad"][0][q] - fd) <= 1e-6 * scale

@@ -9,16 +9,20 @@ import pytest
 from paper_2204_05586_amd import workloads as W
 
 
-def _control_problem(spin_twice, n_seg=6, K=40, L=6, frame=True, tau=24, seed=0):
+def _control_problem(spin_twice, n_seg=6, K=40, L=6, frame=True, tau=24, seed=0,
+                     extra=("cos", "sin", "pwc")):
     """Piecewise-constant controls on x and y plus cos/sin terms whose
-    amplitude, frequency and phase come from slots."""
+    amplitude, frequency and phase come from slots (`extra` picks which)."""
     rng = np.random.default_rng(seed)
     f_bias = 3.0e4
     T = K * 2e-5
     terms = W.control_problem_terms(n_seg=n_seg, seg_t0=0.0, seg_len=T / n_seg, f_bias=f_bias)
-    terms += [W.Term(W.COS, W.X, a_slot=2 * n_seg, f_slot=2 * n_seg + 1, phi_slot=2 * n_seg + 2),
-              W.Term(W.SIN, W.Y, a_slot=2 * n_seg + 3, f=2.1e3, phi=0.3),
-              W.Term(W.PWC, W.Y, n_seg=3, seg_t0=0.0, seg_len=T / 3, seg_a_slot=2 * n_seg + 4)]
+    more = {"cos": W.Term(W.COS, W.X, a_slot=2 * n_seg, f_slot=2 * n_seg + 1,
+                          phi_slot=2 * n_seg + 2),
+            "sin": W.Term(W.SIN, W.Y, a_slot=2 * n_seg + 3, f=2.1e3, phi=0.3),
+            "pwc": W.Term(W.PWC, W.Y, n_seg=3, seg_t0=0.0, seg_len=T / 3,
+                          seg_a_slot=2 * n_seg + 4)}
+    terms += [more[k] for k in extra]
     if spin_twice == 2:
         terms.append(W.Term(W.CONST, W.Q, a=150.0))
     params = np.concatenate([rng.normal(2000.0, 400.0, n_seg), rng.uniform(0, 2 * math.pi, n_seg),
