@@ -111,10 +111,13 @@ def bench_plain(prob, steps: int, warmup: int) -> dict:
             "launch": {"slices": launch[0], "block": launch[1]}, "tau": prob.n_squares}
 
 
-def bench_batched(problems, steps: int, warmup: int, graph_reps: int) -> dict:
+def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool) -> dict:
     import torch
-    from paper_2204_05586_amd import native
-    plan = native.BatchPlan(problems)
+    from paper_2204_05586_amd import autotune, native
+    t0 = time.perf_counter()
+    opts = autotune.tune(problems, cache_path=None) if tune else {}
+    tune_s = time.perf_counter() - t0
+    plan = native.BatchPlan(problems, **opts)
     bufs = plan.allocate(store_u=False)
     stream = torch.cuda.current_stream()
     fine = sum(p.fine_steps for p in problems)
@@ -144,9 +147,9 @@ def bench_batched(problems, steps: int, warmup: int, graph_reps: int) -> dict:
     plan.close()
     out = {"value": fine * steps / wall, "ms_per_step": wall / steps * 1e3,
            "integrate_ms": statistics.mean(integ), "propagate_ms": statistics.mean(prop),
-           "fine_steps": fine, "info": info}
+           "fine_steps": fine, "info": info, "options": opts, "tune_s": tune_s}
     if graph_reps > 0:
-        gplan = native.BatchPlan(problems, use_graph=True)
+        gplan = native.BatchPlan(problems, use_graph=True, **opts)
         gplan.run(bufs, stream=stream)  # capture + first replay
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -213,6 +216,33 @@ def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib:
     return out
 
 
+def bench_adjoint(n_inst: int, steps: int, warmup: int) -> dict:
+    """Gradients of the |0> population w.r.t. 512 piecewise-constant
+    controls (256 amplitudes, 256 phases) for n_inst spin-1 instances of 1
+    ms (1e3 intervals x 100 CF4 steps, tau = 28, resonant rotating frame)."""
+    import torch
+    from paper_2204_05586_amd import native, workloads as W
+    probs = W.control_batch(seed=4, n_inst=n_inst)
+    plan = native.AdjointPlan(probs, 1)
+    bufs = plan.allocate()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.run(bufs, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(bufs, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    fine = sum(p.fine_steps for p in probs)
+    plan.close()
+    del bufs
+    torch.cuda.empty_cache()
+    return {"instances": n_inst, "controls_per_instance": 512, "ms_per_gradient_batch": round(dt * 1e3, 3),
+            "gradients_per_s": round(n_inst * 512 / dt, 1),
+            "forward_plus_adjoint_fine_steps_per_s": round(fine / dt, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,12 +253,15 @@ def main():
     ap.add_argument("--n-sims", type=int, default=4096, help="batch size of batched_sensing")
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--graph-reps", type=int, default=2)
+    ap.add_argument("--no-tune", action="store_true", help="planner defaults, no autotuning")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
                     help="target CPU seconds of the oracle sample (0: skip)")
     ap.add_argument("--serve-rates", default="10,100,1000",
                     help="request rates (req/s) of the serving sweep, '' to skip")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="target stream length per rate (requests = rate x seconds, <= 2000)")
+    ap.add_argument("--adjoint-instances", type=int, default=1024,
+                    help="instances of the control-gradient workload (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -246,7 +279,7 @@ def main():
     if args.workload == "batched_sensing":
         problems = W.batched_sensing(seed=2, n_sims=args.n_sims)
         tau = problems[0].n_squares
-        res = bench_batched(problems, args.steps, args.warmup, args.graph_reps)
+        res = bench_batched(problems, args.steps, args.warmup, args.graph_reps, not args.no_tune)
         kernel = "batch_integrate_kernel"
         plain = bench_plain(W.spin_one_sensing(), args.plain_steps, 3)
         value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
@@ -257,7 +290,8 @@ def main():
                   "n_sims": len(problems), "total_intervals": res["info"]["total_samples"],
                   "n_fine": 10, "fine_steps": fine, "n_squares": tau, "rotating_frame": True,
                   "work_items": res["info"]["n_items"], "grid_blocks": res["info"]["grid_blocks"],
-                  "scan_levels": res["info"]["scan_levels"]}
+                  "scan_levels": res["info"]["scan_levels"], "autotuned": res["options"],
+                  "autotune_s": round(res["tune_s"], 2)}
         extra = {"integrate_ms_mean": round(integ_ms, 3),
                  "propagate_ms_mean": round(res["propagate_ms"], 3),
                  "graph_ms_per_step": round(res.get("graph_ms_per_step", 0.0), 3) or None,
@@ -301,6 +335,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    adjoint = None
+    if args.adjoint_instances > 0:
+        adjoint = bench_adjoint(args.adjoint_instances, 3, 1)
+
     serving = None
     if args.serve_rates:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
@@ -325,6 +363,7 @@ def main():
         "config": config,
         **extra,
         "latency": serving,
+        "adjoint": adjoint,
         "roofline": roofline,
         "cpu_baseline": base,
         "kernel_src": src_hash,

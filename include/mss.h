@@ -194,6 +194,7 @@ typedef struct mss_batch_options {
   int32_t waves_per_simd;   /* persistent grid: resident waves per SIMD (0: 2) */
   int32_t use_graph;        /* 1: capture the batch as one HIP graph, replayed while the
                                buffer pointers stay the same */
+  int32_t scan_per_lane;    /* operators per lane in the scan tiles: 2, 4 or 8 (0: 4) */
 } mss_batch_options;
 
 typedef struct mss_batch_info_t {

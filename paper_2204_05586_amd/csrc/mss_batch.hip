@@ -131,6 +131,10 @@ mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const i
     return api_fail(MSS_E_INVALID, "slices must be 0 (choose) or a power of two <= 64");
   if (opt.waves_per_simd < 0 || opt.waves_per_simd > 8)
     return api_fail(MSS_E_INVALID, "waves_per_simd must be in [0, 8]");
+  if (opt.scan_per_lane != 0 && opt.scan_per_lane != 2 && opt.scan_per_lane != 4 &&
+      opt.scan_per_lane != 8)
+    return api_fail(MSS_E_INVALID, "scan_per_lane must be 0, 2, 4 or 8");
+  const int scan_e = opt.scan_per_lane ? opt.scan_per_lane : kScanPerLane;
   for (int i = 0; i < n; ++i) {
     mss_status s = api_validate_problem(&problems[i]);
     if (s != MSS_OK) {
@@ -159,6 +163,7 @@ mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const i
   if (!P) return api_fail(MSS_E_NOMEM, "host allocation failed");
   P->n = n;
   P->opt = opt;
+  P->work.scan_e = scan_e;
   P->psi0_off.assign(n + 1, 0);
   P->state_off.assign(n + 1, 0);
   P->op_off.assign(n + 1, 0);
@@ -173,7 +178,7 @@ mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const i
     P->op_off[i + 1] = P->op_off[i] + q.n_samples * N * N;
     P->param_off[i] = q.n_params > 0 ? param_off[i] : 0;
     P->scan_off[i] = scan;
-    scan += scan_scratch_bytes(N, q.n_samples);
+    scan += scan_scratch_bytes(N, q.n_samples, 64 * scan_e);
     int S = S_class[q.spin_twice - 1];
     while (S > q.n_fine) S >>= 1;
     P->work.add(q, api_ilog2(S), 0, q.n_samples, true);

@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(256) scan_reduce_kernel(const double* __restri
   const int lane = threadIdx.x & 63;
   const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
-  tile_reduce<N>(M, n, tile, lane, tile < ntiles ? agg + (size_t)tile * 2 * N * N : nullptr);
+  tile_reduce<N, kScanPerLane>(M, n, tile, lane, tile < ntiles ? agg + (size_t)tile * 2 * N * N : nullptr);
 }
 
 template <int N>
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const double* __restric
   const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   const bool valid = tile < ntiles;
-  tile_apply<N>(M, n, tile, lane, valid, valid ? start + (size_t)tile * 2 * N : nullptr, before,
+  tile_apply<N, kScanPerLane>(M, n, tile, lane, valid, valid ? start + (size_t)tile * 2 * N : nullptr, before,
                 after_last);
 }
 

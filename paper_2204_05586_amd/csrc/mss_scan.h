@@ -1,19 +1,19 @@
 // Tile routines of the ordered prefix product psi_{k+1} = U_k psi_k
-// (eq. integration_compilation): one wave owns a tile of kScanTile
-// consecutive N x N operators, each lane a run of kScanPerLane of them.
+// (eq. integration_compilation): one wave owns a tile of 64 E consecutive
+// N x N operators, each lane a run of E of them.
 #pragma once
 
 #include "mss_internal.h"
 
 namespace mss {
 
-// Product of the lane's (up to) kScanPerLane consecutive matrices, later on the left.
-template <int N>
+// Product of the lane's (up to) E consecutive matrices, later on the left.
+template <int N, int E>
 __device__ __forceinline__ void lane_product(const double* __restrict__ M, int64_t n, int64_t base,
                                              Mat<N>& Q) {
   set_identity<N>(Q);
 #pragma unroll
-  for (int e = 0; e < kScanPerLane; ++e) {
+  for (int e = 0; e < E; ++e) {
     const int64_t idx = base + e;
     if (idx < n) {
       Mat<N> X;
@@ -23,14 +23,14 @@ __device__ __forceinline__ void lane_product(const double* __restrict__ M, int64
   }
 }
 
-// Tile reduce: agg = M[tT + T - 1] ... M[tT] of tile t (T = kScanTile), one
+// Tile reduce: agg = M[tT + T - 1] ... M[tT] of tile t (T = 64 E), one
 // wave per tile.  M points at element 0 of the sequence, n its length.
-template <int N>
+template <int N, int E>
 __device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_t n, int64_t tile,
                                             int lane, double* __restrict__ agg_out) {
-  const int64_t base = tile * kScanTile + (int64_t)lane * kScanPerLane;
+  const int64_t base = tile * (64 * E) + (int64_t)lane * E;
   Mat<N> Q;
-  lane_product<N>(M, n, base, Q);
+  lane_product<N, E>(M, n, base, Q);
   for (int d = 1; d < 64; d <<= 1) {
     const Mat<N> o = shfl_down_mat<N>(Q, d);
     if ((lane & (2 * d - 1)) == 0) premultiply<N>(o, Q);
@@ -41,14 +41,14 @@ __device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_
 // Tile apply: before[i] = M[i-1] ... M[tT] start for i in tile t (the state
 // entering element i); after_last (optional) receives M[n-1] ... applied
 // when the tile holds the last element.  Every lane must call this.
-template <int N>
+template <int N, int E>
 __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t n, int64_t tile,
                                            int lane, bool valid, const double* __restrict__ start,
                                            double* __restrict__ before,
                                            double* __restrict__ after_last) {
-  const int64_t base = tile * kScanTile + (int64_t)lane * kScanPerLane;
+  const int64_t base = tile * (64 * E) + (int64_t)lane * E;
   Mat<N> P;
-  lane_product<N>(M, n, base, P);
+  lane_product<N, E>(M, n, base, P);
   // inclusive scan over lanes: P_lane = Q_lane ... Q_0
   for (int d = 1; d < 64; d <<= 1) {
     const Mat<N> o = shfl_up_mat<N>(P, d);
@@ -85,7 +85,7 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
     }
   }
 #pragma unroll
-  for (int e = 0; e < kScanPerLane; ++e) {
+  for (int e = 0; e < E; ++e) {
     const int64_t idx = base + e;
     if (idx < n) {
       double* o = before + (size_t)idx * 2 * N;

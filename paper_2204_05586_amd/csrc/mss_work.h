@@ -33,14 +33,15 @@ struct SimDesc {
   int32_t tau, frame, slices_log2, top;  // top: scan levels above 0; -1: no scan
 };
 
-// Scan geometry of a sequence of K operators: levels above 0 and the
-// scratch (bytes) of levels 1..top.
-int scan_top(int64_t K);
-size_t scan_scratch_bytes(int N, int64_t K);
+// Scan geometry of a sequence of K operators with tiles of `tile`
+// (= 64 E) operators: levels above 0 and the scratch (bytes) of levels 1..top.
+int scan_top(int64_t K, int tile = kScanTile);
+size_t scan_scratch_bytes(int N, int64_t K, int tile = kScanTile);
 
 // Host-side builder: fills item offsets and the scan tile tables, then
 // packs everything for one upload.
 struct WorkSet {
+  int scan_e = kScanPerLane;  // operators per lane in the scan: 2, 4 or 8
   std::vector<SimDesc> sims;
   std::vector<mss_term> terms;
   int64_t n_items = 0;
@@ -72,6 +73,7 @@ struct DevWork {
   int32_t n_sims = 0;
   int64_t n_items = 0;
   int n_levels = 0;
+  int scan_e = kScanPerLane;
 };
 
 DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_t o_terms,

@@ -15,11 +15,11 @@
 
 namespace mss {
 
-int scan_top(int64_t K) {
+int scan_top(int64_t K, int tile) {
   int top = 0;
   int64_t n = K;
-  while (n > kScanTile) {
-    n = (n + kScanTile - 1) / kScanTile;
+  while (n > tile) {
+    n = (n + tile - 1) / tile;
     ++top;
   }
   return top;
@@ -27,11 +27,11 @@ int scan_top(int64_t K) {
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t scan_scratch_bytes(int N, int64_t K) {
+size_t scan_scratch_bytes(int N, int64_t K, int tile) {
   size_t b = 0;
   int64_t n = K;
-  while (n > kScanTile) {
-    n = (n + kScanTile - 1) / kScanTile;
+  while (n > tile) {
+    n = (n + tile - 1) / tile;
     b += (size_t)n * (N * N + N) * 16;
   }
   return a256(b);
@@ -114,36 +114,36 @@ __global__ void __launch_bounds__(256) work_integrate_kernel(const IntegrateWork
 
 // Element count of a sequence at a scan level and the start of that level's
 // arrays in the sequence's scratch (levels >= 1).
-template <int N>
+template <int N, int E>
 __device__ __forceinline__ int64_t level_geometry(const SimDesc& s, int level, size_t* mats_off) {
   int64_t n = s.K_total;
   size_t off = 0;
   for (int l = 1; l <= level; ++l) {
     if (l > 1) off += (size_t)n * (N * N + N) * 2;
-    n = (n + kScanTile - 1) / kScanTile;
+    n = (n + 64 * E - 1) / (64 * E);
   }
   *mats_off = off;  // in doubles
   return n;
 }
 
-template <int N>
+template <int N, int E>
 __device__ __forceinline__ void work_reduce_tile(const SimDesc& s, int level, int64_t local,
                                                  int lane) {
   size_t off = 0;
-  const int64_t n = level_geometry<N>(s, level, &off);
+  const int64_t n = level_geometry<N, E>(s, level, &off);
   const double* M = level == 0 ? s.U : s.scan_ws + off;
   size_t up_off = 0;
-  const int64_t n_up = level_geometry<N>(s, level + 1, &up_off);
+  const int64_t n_up = level_geometry<N, E>(s, level + 1, &up_off);
   (void)n_up;
   double* out = s.scan_ws + up_off + (size_t)local * 2 * N * N;
-  tile_reduce<N>(M, n, local, lane, out);
+  tile_reduce<N, E>(M, n, local, lane, out);
 }
 
-template <int N>
+template <int N, int E>
 __device__ __forceinline__ void work_apply_tile(const SimDesc& s, int level, int64_t local,
                                                 int lane) {
   size_t off = 0;
-  const int64_t n = level_geometry<N>(s, level, &off);
+  const int64_t n = level_geometry<N, E>(s, level, &off);
   const double* M = level == 0 ? s.U : s.scan_ws + off;
   double* before = level == 0 ? s.psi : s.scan_ws + off + (size_t)n * 2 * N * N;
   const double* start;
@@ -151,12 +151,13 @@ __device__ __forceinline__ void work_apply_tile(const SimDesc& s, int level, int
     start = s.psi0;
   } else {
     size_t up_off = 0;
-    const int64_t n_up = level_geometry<N>(s, level + 1, &up_off);
+    const int64_t n_up = level_geometry<N, E>(s, level + 1, &up_off);
     start = s.scan_ws + up_off + (size_t)n_up * 2 * N * N + (size_t)local * 2 * N;
   }
-  tile_apply<N>(M, n, local, lane, true, start, before, level == 0 ? s.psi_final : nullptr);
+  tile_apply<N, E>(M, n, local, lane, true, start, before, level == 0 ? s.psi_final : nullptr);
 }
 
+template <int E>
 __global__ void __launch_bounds__(256) work_reduce_kernel(const ScanWorkArgs A) {
   const int lane = threadIdx.x & 63;
   const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -164,10 +165,11 @@ __global__ void __launch_bounds__(256) work_reduce_kernel(const ScanWorkArgs A) 
   const int i = find_segment(A.tiles, A.n_sims, tile);
   const int64_t local = tile - A.tiles[i];
   const SimDesc& s = A.sims[i];
-  if (s.spin_twice == 2) work_reduce_tile<3>(s, A.level, local, lane);
-  else work_reduce_tile<2>(s, A.level, local, lane);
+  if (s.spin_twice == 2) work_reduce_tile<3, E>(s, A.level, local, lane);
+  else work_reduce_tile<2, E>(s, A.level, local, lane);
 }
 
+template <int E>
 __global__ void __launch_bounds__(256) work_apply_kernel(const ScanWorkArgs A) {
   const int lane = threadIdx.x & 63;
   const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -175,8 +177,8 @@ __global__ void __launch_bounds__(256) work_apply_kernel(const ScanWorkArgs A) {
   const int i = find_segment(A.tiles, A.n_sims, tile);
   const int64_t local = tile - A.tiles[i];
   const SimDesc& s = A.sims[i];
-  if (s.spin_twice == 2) work_apply_tile<3>(s, A.level, local, lane);
-  else work_apply_tile<2>(s, A.level, local, lane);
+  if (s.spin_twice == 2) work_apply_tile<3, E>(s, A.level, local, lane);
+  else work_apply_tile<2, E>(s, A.level, local, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -198,7 +200,7 @@ void WorkSet::add(const mss_problem& p, int slices_log2, int64_t k_first, int64_
   d.tau = p.spin_twice == 2 ? p.n_squares : 0;
   d.frame = p.rotating_frame;
   d.slices_log2 = slices_log2;
-  d.top = scan ? scan_top(p.n_samples) : -1;
+  d.top = scan ? scan_top(p.n_samples, 64 * scan_e) : -1;
   if (last_terms_ && last_n_terms_ == p.n_terms &&
       (p.n_terms == 0 || memcmp(last_terms_, p.terms, sizeof(mss_term) * p.n_terms) == 0)) {
     d.term_off = last_term_off_;
@@ -225,11 +227,12 @@ void WorkSet::finalize() {
   n_items = item;
   reduce_tiles.assign(n_levels, std::vector<int64_t>(n + 1, 0));
   apply_tiles.assign(n_levels + 1, std::vector<int64_t>(n + 1, 0));
+  const int tile = 64 * scan_e;
   for (int i = 0; i < n; ++i) {
     const SimDesc& d = sims[i];
     int64_t cnt = d.K_total;
     for (int l = 0; l <= n_levels; ++l) {
-      const int64_t tiles = (cnt + kScanTile - 1) / kScanTile;
+      const int64_t tiles = (cnt + tile - 1) / tile;
       const bool scans = d.top >= 0;
       if (l < n_levels) reduce_tiles[l][i + 1] = reduce_tiles[l][i] + (scans && l < d.top ? tiles : 0);
       apply_tiles[l][i + 1] = apply_tiles[l][i] + (scans && l <= d.top ? tiles : 0);
@@ -276,6 +279,7 @@ DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_
   d.n_sims = (int32_t)w.sims.size();
   d.n_items = w.n_items;
   d.n_levels = w.n_levels;
+  d.scan_e = w.scan_e;
   for (size_t l = 0; l < o_reduce.size(); ++l) {
     d.reduce_tiles.push_back((const int64_t*)(dev_base + o_reduce[l]));
     d.reduce_total.push_back(w.reduce_tiles[l].back());
@@ -296,19 +300,28 @@ hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, 
   return hipGetLastError();
 }
 
-hipError_t launch_work_scan(const DevWork& w, hipStream_t st) {
+template <int E>
+static void scan_levels(const DevWork& w, hipStream_t st) {
   for (int l = 0; l < w.n_levels; ++l) {
     const int64_t tiles = w.reduce_total[l];
     if (!tiles) continue;
     ScanWorkArgs a{w.sims, w.reduce_tiles[l], tiles, w.n_sims, l};
-    hipLaunchKernelGGL(work_reduce_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(work_reduce_kernel<E>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st,
+                       a);
   }
   for (int l = w.n_levels; l >= 0; --l) {
     const int64_t tiles = w.apply_total[l];
     if (!tiles) continue;
     ScanWorkArgs a{w.sims, w.apply_tiles[l], tiles, w.n_sims, l};
-    hipLaunchKernelGGL(work_apply_kernel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(work_apply_kernel<E>, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st,
+                       a);
   }
+}
+
+hipError_t launch_work_scan(const DevWork& w, hipStream_t st) {
+  if (w.scan_e == 2) scan_levels<2>(w, st);
+  else if (w.scan_e == 8) scan_levels<8>(w, st);
+  else scan_levels<4>(w, st);
   return hipGetLastError();
 }
 

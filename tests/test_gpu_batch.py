@@ -134,3 +134,21 @@ def test_batch_rejects_bad_members(torch_dev):
     probs[1] = probs[1].replace(n_samples=0)
     with pytest.raises(native.MssError, match="simulation 1"):
         native.BatchPlan(probs)
+
+
+def test_autotuned_plan_matches_oracle(torch_dev, oracle, tmp_path):
+    """The autotuner picks valid options (cached on disk, reused on the
+    second call) and the tuned plan still matches the oracle."""
+    from paper_2204_05586_amd import autotune, native
+    probs = W.batched_sensing(seed=8, n_sims=40, dur_lo=0.001, dur_hi=0.004)
+    cache = str(tmp_path / "tune.json")
+    opts = autotune.tune(probs, cache_path=cache, reps=2, target_fine_steps=2e7, verbose=True)
+    assert opts["scan_per_lane"] in (2, 4, 8) and opts["waves_per_simd"] in (1, 2, 4)
+    assert autotune.tune(probs, cache_path=cache) == opts
+    plan = native.BatchPlan(probs, **opts)
+    bufs = _run(plan, store_u=False)
+    for i in (0, 17, 39):
+        ref = oracle.solve(probs[i])
+        got = plan.split(bufs, i)
+        assert np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"])) <= TOL
+    plan.close()
