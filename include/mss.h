@@ -108,7 +108,16 @@ typedef struct mss_problem {
   double dt_out;          /* Dt > 0, s */
   int32_t n_squares;      /* tau in [0, MSS_MAX_SQUARES], spin-1 only (paper default 24) */
   int32_t rotating_frame; /* 0/1: per-interval frame at omega_r = 2 pi f_z(t_k + Dt/2) */
+  int32_t method;         /* mss_method (0: CF4) */
 } mss_problem;
+
+/* Integration method per fine step (Sec. "Evaluation of accuracy" compares
+ * the first with the other two):
+ *   MSS_CF4       exp(-i Hbar_2 dt) exp(-i Hbar_1 dt), Gauss nodes (default)
+ *   MSS_MIDPOINT  exp(-i H(t + dt/2) dt)                ("modified Euler")
+ *   MSS_HEUN      exp(-i (H(t) + H(t + dt))/2 dt)        ("improved Euler")
+ * The adjoint supports MSS_CF4 only. */
+typedef enum mss_method { MSS_CF4 = 0, MSS_MIDPOINT = 1, MSS_HEUN = 2 } mss_method;
 
 /* Launch shape of the integrator.  slices: lanes cooperating on one
  * interval (power of two, 1..64, <= n_fine); each lane takes a contiguous
@@ -161,6 +170,13 @@ mss_status mss_integrate(const mss_problem* p, const double* params, double* U, 
 mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
                          const double* psi0, double* psi, double* psi_final, void* ws,
                          size_t ws_bytes, void* stream);
+
+/* Expected spin projection <J_x>, <J_y>, <J_z> of each state (Sec.
+ * "Quantum mechanics background": the measurable ensemble average of the
+ * spin): out[3k + a] = psi_k^H J_a psi_k.  psi: device [n_samples][N]
+ * complex; out: device [n_samples][3] doubles. */
+mss_status mss_spin_projection(int32_t spin_twice, int64_t n_samples, const double* psi,
+                               double* out, void* stream);
 
 /* Whole path: mss_integrate then mss_propagate.  U may be NULL (the
  * operators then live in the workspace, see mss_workspace_size). */

@@ -63,6 +63,7 @@ struct OProblem {
   int32_t n_squares;   // tau
   int32_t rotating_frame;
   int32_t n_params;
+  int32_t method;      // 0: CF4, 1: midpoint (modified Euler), 2: Heun (improved Euler)
   int64_t n_samples;   // K
   double t_start;
   double dt_out;       // Dt
@@ -316,10 +317,20 @@ Mat<R, N> interval_operator(const OProblem& p, const R* params, int64_t k) {
     wr = two_pi<R>() * f[2];
   }
   Mat<R, N> U = Mat<R, N>::identity();
+  // sampling nodes (fractions of the fine step) and number of exponentials
+  // per step: CF4 two Gauss nodes and two exponentials; the Euler-family
+  // comparison methods one exponential of H sampled at the midpoint, or of
+  // the average of H at both ends of the step (Sec. "Evaluation of accuracy").
+  const int nn = p.method == 1 ? 1 : 2;
+  R cnode[2] = {c1, c2};
+  if (p.method == 1) cnode[0] = R(1) / R(2);
+  if (p.method == 2) {
+    cnode[0] = R(0);
+    cnode[1] = R(1);
+  }
   for (int l = 0; l < p.n_fine; ++l) {
     R w[2][4];
-    const R cnode[2] = {c1, c2};
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < nn; ++i) {
       const R tau_i = (R(l) + cnode[i]) * dt;
       R f[4];
       field<R>(p, params, tk + tau_i, f);
@@ -331,13 +342,19 @@ Mat<R, N> interval_operator(const OProblem& p, const R* params, int64_t k) {
       w[i][2] = w[i][2] - wr;
     }
     R th1[4], th2[4];
-    for (int j = 0; j < 4; ++j) {
-      th1[j] = (wp * w[0][j] + wm * w[1][j]) * dt;
-      th2[j] = (wm * w[0][j] + wp * w[1][j]) * dt;
+    if (p.method == 0) {
+      for (int j = 0; j < 4; ++j) {
+        th1[j] = (wp * w[0][j] + wm * w[1][j]) * dt;
+        th2[j] = (wm * w[0][j] + wp * w[1][j]) * dt;
+      }
+      Mat<R, N> E1 = Exp<R, N>::apply(th1, p.n_squares);
+      Mat<R, N> E2 = Exp<R, N>::apply(th2, p.n_squares);
+      U = matmul(E2, matmul(E1, U));
+    } else {
+      for (int j = 0; j < 4; ++j)
+        th1[j] = (p.method == 1 ? w[0][j] : (w[0][j] + w[1][j]) / R(2)) * dt;
+      U = matmul(Exp<R, N>::apply(th1, p.n_squares), U);
     }
-    Mat<R, N> E1 = Exp<R, N>::apply(th1, p.n_squares);
-    Mat<R, N> E2 = Exp<R, N>::apply(th2, p.n_squares);
-    U = matmul(E2, matmul(E1, U));
   }
   // leave the rotating frame: U_k = diag(exp(-i m omega_r Dt)) U_k^r
   for (int i = 0; i < N; ++i) {
@@ -664,11 +681,43 @@ int oracle_states(int spin_twice, int64_t K, const double* U, const double* psi0
   return 0;
 }
 
+// Expected spin projection <J_a>_k = psi_k^H J_a psi_k, a = x, y, z, with the
+// spin matrices written out (Sec. "Quantum mechanics background").
+int oracle_spin_projection(int spin_twice, int64_t K, const double* psi, double* out) {
+  const int N = spin_twice + 1;
+  if (N != 2 && N != 3) return 1;
+  const double h = 0.5, r = 1.0 / std::sqrt(2.0);
+  cx<double> J[3][3][3] = {};
+  if (N == 2) {
+    J[0][0][1] = h; J[0][1][0] = h;
+    J[1][0][1] = cx<double>(0, -h); J[1][1][0] = cx<double>(0, h);
+    J[2][0][0] = h; J[2][1][1] = -h;
+  } else {
+    J[0][0][1] = r; J[0][1][0] = r; J[0][1][2] = r; J[0][2][1] = r;
+    J[1][0][1] = cx<double>(0, -r); J[1][1][0] = cx<double>(0, r);
+    J[1][1][2] = cx<double>(0, -r); J[1][2][1] = cx<double>(0, r);
+    J[2][0][0] = 1; J[2][2][2] = -1;
+  }
+  for (int64_t k = 0; k < K; ++k) {
+    cx<double> v[3];
+    for (int i = 0; i < N; ++i) v[i] = cx<double>(psi[2 * (k * N + i)], psi[2 * (k * N + i) + 1]);
+    for (int a = 0; a < 3; ++a) {
+      cx<double> s(0, 0);
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) s += std::conj(v[i]) * J[a][i][j] * v[j];
+      out[3 * k + a] = s.real();
+    }
+  }
+  return 0;
+}
+
 // loss = |psi_final[m]|^2 and grad[q] = dloss/dparams[q] for q < n_params.
-// Returns 1 on bad arguments, 2 if a z or q term uses a parameter slot.
+// Returns 1 on bad arguments, 2 if a z or q term uses a parameter slot, 3 for
+// a method other than CF4.
 int oracle_adjoint_population(const OProblem* p, const double* params, const double* psi0, int m,
                               double* loss, double* grad) {
   if (!p || p->n_samples < 1 || p->n_fine < 1 || m < 0 || m > p->spin_twice) return 1;
+  if (p->method != 0) return 3;
   for (int i = 0; i < p->n_terms; ++i) {
     const OTerm& t = p->terms[i];
     const bool slots = t.a_slot >= 0 || t.f_slot >= 0 || t.phi_slot >= 0 || t.seg_a_slot >= 0 ||

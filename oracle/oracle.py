@@ -5,7 +5,7 @@ benchmark's CPU-baseline leg are the only callers.  Nothing in the GPU
 library imports this module, and this module imports nothing from the GPU
 library: problems are passed duck-typed (any object with the attributes
 ``spin_twice, terms, t_start, dt_out, n_samples, n_fine, n_squares,
-rotating_frame, params, psi0``; terms with ``kind, comp, a, f, phi, a_slot,
+rotating_frame, params, psi0`` and optionally ``method``; terms with ``kind, comp, a, f, phi, a_slot,
 f_slot, phi_slot, t_on, t_off, n_seg, seg_t0, seg_len, seg_a_slot,
 seg_phi_slot``).
 
@@ -49,7 +49,7 @@ class _Term(C.Structure):
 class _Problem(C.Structure):
     _fields_ = [("spin_twice", C.c_int32), ("n_terms", C.c_int32), ("n_fine", C.c_int32),
                 ("n_squares", C.c_int32), ("rotating_frame", C.c_int32), ("n_params", C.c_int32),
-                ("n_samples", C.c_int64), ("t_start", C.c_double), ("dt_out", C.c_double),
+                ("method", C.c_int32), ("n_samples", C.c_int64), ("t_start", C.c_double), ("dt_out", C.c_double),
                 ("terms", C.POINTER(_Term))]
 
 
@@ -75,6 +75,8 @@ def lib():
         L.oracle_states.restype = C.c_int
         L.oracle_solve.argtypes = [C.POINTER(_Problem), dp, dp, dp, dp, dp]
         L.oracle_solve.restype = C.c_int
+        L.oracle_spin_projection.argtypes = [C.c_int, C.c_int64, dp, dp]
+        L.oracle_spin_projection.restype = C.c_int
         L.oracle_adjoint_population.argtypes = [C.POINTER(_Problem), dp, dp, C.c_int, dp, dp]
         L.oracle_adjoint_population.restype = C.c_int
         ldp = C.c_void_p
@@ -103,7 +105,8 @@ class _Packed:
         params = np.ascontiguousarray(np.asarray(prob.params, dtype=np.float64).ravel())
         self.params = params if params.size else np.zeros(1)
         self.p = _Problem(int(prob.spin_twice), len(terms), int(prob.n_fine), int(prob.n_squares),
-                          int(bool(prob.rotating_frame)), int(params.size), int(prob.n_samples),
+                          int(bool(prob.rotating_frame)), int(params.size),
+                          int(getattr(prob, "method", 0)), int(prob.n_samples),
                           float(prob.t_start), float(prob.dt_out), arr)
         self.dim = int(prob.spin_twice) + 1
 
@@ -224,6 +227,8 @@ def adjoint_population(prob, m: int) -> tuple[float, np.ndarray]:
                                          int(m), _dp(loss), _dp(grad))
     if rc == 2:
         raise ValueError("gradients need parameter slots on x and y terms only")
+    if rc == 3:
+        raise ValueError("gradients need the CF4 method")
     if rc:
         raise ValueError("oracle_adjoint_population: bad arguments")
     return float(loss[0]), grad[:pk.p.n_params].copy()
@@ -233,3 +238,14 @@ def population_ld(prob, m: int, params_ld: np.ndarray) -> np.longdouble:
     """|psi_final[m]|^2 in extended precision at the given parameters."""
     out = final_state_ld(prob, params_ld)
     return out[m, 0] * out[m, 0] + out[m, 1] * out[m, 1]
+
+
+def spin_projection(psi: np.ndarray) -> np.ndarray:
+    """<J_x>, <J_y>, <J_z> of each state row of psi [K, N] -> [K, 3]."""
+    psi = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    K, N = psi.shape
+    out = np.zeros((K, 3))
+    rc = lib().oracle_spin_projection(N - 1, K, _dp(psi.view(np.float64)), _dp(out))
+    if rc:
+        raise ValueError("oracle_spin_projection: bad arguments")
+    return out

@@ -356,7 +356,7 @@ template <int N>
 __device__ __forceinline__ void adjoint_interval(const AdjArgs& A, const AdjDesc& s, int64_t k) {
   const TableTerms terms{A.terms + s.term_off, s.n_terms};
   double tk, wr;
-  interval_setup(terms, s.params, s.t_start, s.dt_out, k, s.frame, &tk, &wr);
+  interval_setup(terms, s.params, s.t_start, s.dt_out, k, s.frame, &tk, &wr);  // CF4 only
   // psi_{k+1}, lambda_{k+1} into frame coordinates: R^H x, R = diag(e^{-i m wr Dt})
   const double* pn = (k + 1 < s.K) ? s.psi + (size_t)(k + 1) * 2 * N : s.psi_final;
   const double* ln = s.lam_before + (size_t)(s.K - 1 - k) * 2 * N;
@@ -640,6 +640,8 @@ mss_status mss_adjoint_plan_create(int32_t n, const mss_problem* problems, const
       std::string msg = api_last_error_copy();
       return api_fail(s, "simulation %d: %s", i, msg.c_str());
     }
+    if (q.method != MSS_CF4)
+      return api_fail(MSS_E_UNSUPPORTED, "simulation %d: gradients need the CF4 method", i);
     if (level_m < 0 || level_m > q.spin_twice)
       return api_fail(MSS_E_INVALID, "simulation %d: level %d outside 0..%d", i, level_m,
                       q.spin_twice);

@@ -154,6 +154,8 @@ mss_status validate_problem(const mss_problem* p) {
                 p->n_squares);
   if (p->rotating_frame != 0 && p->rotating_frame != 1)
     return api_fail(MSS_E_INVALID, "rotating_frame must be 0 or 1");
+  if (p->method < MSS_CF4 || p->method > MSS_HEUN)
+    return api_fail(MSS_E_INVALID, "unknown method %d", p->method);
   for (int i = 0; i < p->n_terms; ++i) {
     const mss_term& t = p->terms[i];
     if (t.kind < MSS_TERM_CONST || t.kind > MSS_TERM_PWC_SIN)
@@ -285,6 +287,7 @@ mss_status mss_integrate(const mss_problem* p, const double* params, double* U, 
   a.L = p->n_fine;
   a.tau = p->spin_twice == 2 ? p->n_squares : 0;
   a.frame = p->rotating_frame;
+  a.method = p->method;
   a.slices_log2 = ilog2(S);
   hipError_t e = launch_integrate(p->spin_twice + 1, a, B, (hipStream_t)stream);
   if (e != hipSuccess) return api_hip_fail(e, "integrate launch");
@@ -320,6 +323,18 @@ mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
     e = launch_scan_apply(N, M[l], lv.n[l], start, before, after, st);
     if (e != hipSuccess) return api_hip_fail(e, "scan apply launch");
   }
+  return api_ok();
+}
+
+mss_status mss_spin_projection(int32_t spin_twice, int64_t n_samples, const double* psi,
+                               double* out, void* stream) {
+  if (spin_twice != 1 && spin_twice != 2) return api_fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
+  if (n_samples < 0) return api_fail(MSS_E_INVALID, "n_samples must be >= 0");
+  if (n_samples == 0) return api_ok();
+  if (!psi || !out) return api_fail(MSS_E_INVALID, "psi and out are required");
+  if ((n_samples + 255) / 256 > 0x7fffffffLL) return api_fail(MSS_E_INVALID, "too many samples");
+  hipError_t e = launch_spin_projection(spin_twice + 1, psi, n_samples, out, (hipStream_t)stream);
+  if (e != hipSuccess) return api_hip_fail(e, "spin projection launch");
   return api_ok();
 }
 

@@ -409,6 +409,36 @@ __device__ __forceinline__ void cf4_angles(const Terms& fp, const double* __rest
   }
 }
 
+// Angles of one Euler-family step (one exponential): H sampled at the
+// midpoint (method 1) or averaged over both ends of the step (method 2).
+template <class Terms>
+__device__ __forceinline__ void euler_angles(const Terms& fp, const double* __restrict__ params,
+                                             double tk, int l, double dt, double wr, int method,
+                                             double th[4]) {
+#pragma clang fp contract(off)
+  const int nn = method == 1 ? 1 : 2;
+  double w[2][4];
+  for (int i = 0; i < nn; ++i) {
+    const double c = method == 1 ? 0.5 : (i == 0 ? 0.0 : 1.0);
+    const double tau_i = ((double)l + c) * dt;
+    double f[4];
+    field_eval(fp, params, tk + tau_i, f);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[i][j] = kTwoPi * f[j];
+    if (wr != 0.0) {
+      double s, cs;
+      sincos_cw(wr * tau_i, &s, &cs);
+      const double xr = w[i][0] * cs + w[i][1] * s;
+      const double xi = w[i][1] * cs - w[i][0] * s;
+      w[i][0] = xr;
+      w[i][1] = xi;
+      w[i][2] = w[i][2] - wr;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) th[j] = (method == 1 ? w[0][j] : (w[0][j] + w[1][j]) / 2.0) * dt;
+}
+
 // Start time of interval k and the frame rate omega_r = 2 pi f_z(t_k + Dt/2).
 template <class Terms>
 __device__ __forceinline__ void interval_setup(const Terms& fp, const double* __restrict__ params,
@@ -454,22 +484,32 @@ __device__ __forceinline__ void exit_frame(double wr, double Dt, Mat<N>& U) {
 template <int N, class Terms>
 __device__ __forceinline__ void interval_operator(const Terms& terms, const double* __restrict__ params,
                                                   double t_start, double Dt, double dt, int L,
-                                                  int tau, int frame, int64_t k, int s, int sl,
-                                                  bool active, Mat<N>& U, double* tk_out) {
+                                                  int tau, int frame, int method, int64_t k, int s,
+                                                  int sl, bool active, Mat<N>& U, double* tk_out) {
   set_identity<N>(U);
   double tk = 0.0, wr = 0.0;
   if (active) {
     interval_setup(terms, params, t_start, Dt, k, frame, &tk, &wr);
     const int l0 = (int)(((int64_t)s * L) >> sl);
     const int l1 = (int)(((int64_t)(s + 1) * L) >> sl);
-    for (int l = l0; l < l1; ++l) {
-      double th1[4], th2[4];
-      cf4_angles(terms, params, tk, l, dt, wr, th1, th2);
-      Mat<N> E;
-      Exponentiator<N>::apply(th1, tau, E);
-      premultiply<N>(E, U);
-      Exponentiator<N>::apply(th2, tau, E);
-      premultiply<N>(E, U);
+    if (method == 0) {
+      for (int l = l0; l < l1; ++l) {
+        double th1[4], th2[4];
+        cf4_angles(terms, params, tk, l, dt, wr, th1, th2);
+        Mat<N> E;
+        Exponentiator<N>::apply(th1, tau, E);
+        premultiply<N>(E, U);
+        Exponentiator<N>::apply(th2, tau, E);
+        premultiply<N>(E, U);
+      }
+    } else {
+      for (int l = l0; l < l1; ++l) {
+        double th[4];
+        euler_angles(terms, params, tk, l, dt, wr, method, th);
+        Mat<N> E;
+        Exponentiator<N>::apply(th, tau, E);
+        premultiply<N>(E, U);
+      }
     }
   }
   for (int d = 1; d < (1 << sl); d <<= 1) {

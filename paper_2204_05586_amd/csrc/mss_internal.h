@@ -27,6 +27,7 @@ struct IntegrateArgs {
   int32_t tau;
   int32_t frame;
   int32_t slices_log2;
+  int32_t method;
 };
 
 // host helpers shared by the C-ABI translation units (mss_api.hip)
@@ -43,5 +44,8 @@ hipError_t launch_integrate(int N, const IntegrateArgs& a, int block, hipStream_
 hipError_t launch_scan_reduce(int N, const double* M, int64_t n, double* agg, hipStream_t st);
 hipError_t launch_scan_apply(int N, const double* M, int64_t n, const double* start, double* before,
                              double* after_last, hipStream_t st);
+
+hipError_t launch_spin_projection(int N, const double* psi, int64_t K, double* out,
+                                  hipStream_t st);
 
 }  // namespace mss

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(256) integrate_kernel(const IntegrateArgs A) {
   Mat<N> U;
   double tk;
   interval_operator<N>(ArgTerms{A.fp}, A.params, A.t_start, A.dt_out, A.dt, A.L, A.tau, A.frame,
-                       k, s, sl, active, U, &tk);
+                       A.method, k, s, sl, active, U, &tk);
   if (active && s == 0) {
     store_mat<N>(A.U + (size_t)k * 2 * N * N, U);
     if (A.time) A.time[k] = tk;
@@ -50,6 +50,36 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const double* __restric
   const bool valid = tile < ntiles;
   tile_apply<N, kScanPerLane>(M, n, tile, lane, valid, valid ? start + (size_t)tile * 2 * N : nullptr, before,
                 after_last);
+}
+
+// <J_a> = psi^H J_a psi for one state per lane (a = x, y, z), written as
+// [K][3] doubles.  Spin-1/2: J = sigma/2; spin-1: J_x, J_y with 1/sqrt 2
+// couplings between neighbouring levels, J_z = diag(1, 0, -1).
+template <int N>
+__global__ void __launch_bounds__(256) spin_projection_kernel(const double* __restrict__ psi,
+                                                              int64_t K, double* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double* v = psi + (size_t)k * 2 * N;
+  double jx, jy, jz;
+  if (N == 2) {
+    const double ar = v[0], ai = v[1], br = v[2], bi = v[3];
+    // <J_x> = Re(conj(a) b), <J_y> = Im(conj(a) b), <J_z> = (|a|^2 - |b|^2) / 2
+    jx = fma(ar, br, ai * bi);
+    jy = fma(ar, bi, -ai * br);
+    jz = 0.5 * (fma(ar, ar, ai * ai) - fma(br, br, bi * bi));
+  } else {
+    const double ar = v[0], ai = v[1], br = v[2], bi = v[3], cr = v[4], ci = v[5];
+    // conj(a) b + conj(b) c, scaled by sqrt 2 (twice the 1/sqrt 2 couplings)
+    const double sr = fma(ar, br, ai * bi) + fma(br, cr, bi * ci);
+    const double si = fma(ar, bi, -ai * br) + fma(br, ci, -bi * cr);
+    jx = 2.0 * kRsqrt2 * sr;
+    jy = 2.0 * kRsqrt2 * si;
+    jz = fma(ar, ar, ai * ai) - fma(cr, cr, ci * ci);
+  }
+  out[3 * k] = jx;
+  out[3 * k + 1] = jy;
+  out[3 * k + 2] = jz;
 }
 
 // ---------------------------------------------------------------------------
@@ -84,6 +114,14 @@ hipError_t launch_scan_apply(int N, const double* M, int64_t n, const double* st
     hipLaunchKernelGGL(scan_apply_kernel<2>, grid, block, 0, st, M, n, start, before, after_last);
   else
     hipLaunchKernelGGL(scan_apply_kernel<3>, grid, block, 0, st, M, n, start, before, after_last);
+  return hipGetLastError();
+}
+
+hipError_t launch_spin_projection(int N, const double* psi, int64_t K, double* out,
+                                  hipStream_t st) {
+  const dim3 grid((unsigned)((K + 255) / 256)), block(256);
+  if (N == 2) hipLaunchKernelGGL(spin_projection_kernel<2>, grid, block, 0, st, psi, K, out);
+  else hipLaunchKernelGGL(spin_projection_kernel<3>, grid, block, 0, st, psi, K, out);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ struct SimDesc {
   double* scan_ws;     // scan levels 1..top: per level [n_l][N][N] then [n_l][N]
   int32_t spin_twice, n_terms, term_off, n_fine;
   int32_t tau, frame, slices_log2, top;  // top: scan levels above 0; -1: no scan
+  int32_t method, pad;
 };
 
 // Scan geometry of a sequence of K operators with tiles of `tile`

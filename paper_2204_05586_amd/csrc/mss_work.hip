@@ -88,7 +88,7 @@ __device__ __forceinline__ void work_item(const IntegrateWorkArgs& A, const SimD
   Mat<N> U;
   double tk;
   interval_operator<N>(TableTerms{A.terms + s.term_off, s.n_terms}, s.params, s.t_start, s.dt_out,
-                       s.dt, s.n_fine, s.tau, s.frame, k, slice, sl, active, U, &tk);
+                       s.dt, s.n_fine, s.tau, s.frame, s.method, k, slice, sl, active, U, &tk);
   if (active && slice == 0) store_mat<N>(s.U + (size_t)k * 2 * N * N, U);
 }
 
@@ -199,6 +199,7 @@ void WorkSet::add(const mss_problem& p, int slices_log2, int64_t k_first, int64_
   d.n_fine = p.n_fine;
   d.tau = p.spin_twice == 2 ? p.n_squares : 0;
   d.frame = p.rotating_frame;
+  d.method = p.method;
   d.slices_log2 = slices_log2;
   d.top = scan ? scan_top(p.n_samples, 64 * scan_e) : -1;
   if (last_terms_ && last_n_terms_ == p.n_terms &&

@@ -25,7 +25,7 @@ MSS_OK, MSS_E_INVALID, MSS_E_NOMEM, MSS_E_DEVICE, MSS_E_UNSUPPORTED, MSS_E_BUSY,
 EXPORTS = [
     "mss_status_str", "mss_last_error", "mss_version", "mss_validate", "mss_plan_launch",
     "mss_workspace_size", "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
-    "mss_solve", "mss_batch_plan_create", "mss_batch_layout", "mss_batch_workspace_size",
+    "mss_solve", "mss_spin_projection", "mss_batch_plan_create", "mss_batch_layout", "mss_batch_workspace_size",
     "mss_batch_info", "mss_batch_run", "mss_batch_integrate", "mss_batch_propagate",
     "mss_batch_plan_destroy", "mss_server_create", "mss_server_submit", "mss_server_poll",
     "mss_server_wait", "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
@@ -60,7 +60,8 @@ class Problem(C.Structure):
     _fields_ = [("spin_twice", C.c_int32), ("n_terms", C.c_int32),
                 ("terms", C.POINTER(Term)), ("n_params", C.c_int32), ("n_fine", C.c_int32),
                 ("n_samples", C.c_int64), ("t_start", C.c_double), ("dt_out", C.c_double),
-                ("n_squares", C.c_int32), ("rotating_frame", C.c_int32)]
+                ("n_squares", C.c_int32), ("rotating_frame", C.c_int32),
+                ("method", C.c_int32)]
 
 
 class Launch(C.Structure):
@@ -121,6 +122,8 @@ def lib() -> C.CDLL:
         L.mss_integrate.argtypes = [PP, vp, vp, vp, C.POINTER(Launch), vp]
         L.mss_propagate.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, vp, vp, sz, vp]
         L.mss_solve.argtypes = [PP, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_spin_projection.argtypes = [C.c_int32, C.c_int64, vp, vp, vp]
+        L.mss_spin_projection.restype = C.c_int
         i64p = C.POINTER(C.c_int64)
         L.mss_batch_plan_create.argtypes = [C.c_int32, PP, i64p, C.POINTER(BatchOptions),
                                             C.POINTER(vp)]
@@ -151,7 +154,7 @@ def lib() -> C.CDLL:
         L.mss_batch_plan_destroy.restype = None
         for name in ("mss_validate", "mss_plan_launch", "mss_workspace_size",
                      "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
-                     "mss_solve", "mss_batch_plan_create", "mss_batch_layout",
+                     "mss_solve", "mss_spin_projection", "mss_batch_plan_create", "mss_batch_layout",
                      "mss_batch_workspace_size", "mss_batch_info", "mss_batch_run",
                      "mss_batch_integrate", "mss_batch_propagate", "mss_server_create",
                      "mss_server_submit", "mss_server_poll", "mss_server_wait",
@@ -191,7 +194,8 @@ class PackedProblem:
         n_params = int(np.asarray(prob.params).size)
         self.c = Problem(int(prob.spin_twice), len(terms), arr, n_params, int(prob.n_fine),
                          int(prob.n_samples), float(prob.t_start), float(prob.dt_out),
-                         int(prob.n_squares), int(bool(prob.rotating_frame)))
+                         int(prob.n_squares), int(bool(prob.rotating_frame)),
+                         int(getattr(prob, "method", 0)))
         self.dim = int(prob.spin_twice) + 1
         self.n_params = n_params
 
@@ -275,6 +279,16 @@ def solve_into(prob, params, psi0, psi, psi_final=None, U=None, time=None, ws=No
     nbytes = 0 if ws is None else int(ws.numel() * ws.element_size())
     check(lib().mss_solve(pk.ref, _ptr(params), _ptr(psi0), _ptr(U), _ptr(psi),
                           _ptr(psi_final), _ptr(time), _ptr(ws), nbytes, _stream(stream)))
+
+
+def spin_projection(psi, stream=None):
+    """<J_x>, <J_y>, <J_z> of each row of a device state tensor [K, N] -> [K, 3]."""
+    import torch
+    K, N = int(psi.shape[0]), int(psi.shape[1])
+    out = torch.empty((K, 3), dtype=torch.float64, device=psi.device)
+    check(lib().mss_spin_projection(N - 1, K, _ptr(psi.contiguous()), _ptr(out),
+                                    _stream(stream)))
+    return out
 
 
 def solve(prob, store_u: bool = False, want_time: bool = False, device="cuda",

@@ -25,6 +25,15 @@ class Results:
     state: "object"            # torch complex128 [K, N]: psi(t_k)
     time_evolution: "object"   # torch complex128 [K, N, N] or None: U_k
     state_final: "object"      # torch complex128 [N]: psi(t_start + K Dt)
+    _spin: "object" = None
+
+    @property
+    def spin(self):
+        """Expected spin projection [K, 3] (<J_x>, <J_y>, <J_z>), computed on
+        first use, as the paper's Results.spin."""
+        if self._spin is None:
+            self._spin = native.spin_projection(self.state)
+        return self._spin
 
 
 def grid_from_times(t_start: float, t_end: float, dt_integration: float, dt_output: float):
@@ -48,12 +57,18 @@ class Simulator:
 
     spin: 0.5 or 1.  terms: field program.  rotating_frame: per-interval
     rotating frame (paper default: on).  n_squares: Lie-Trotter squaring
-    count tau for spin-1 (paper default 24)."""
+    count tau for spin-1 (paper default 24).  method: "cf4" (default), or
+    the Euler-family comparison samplings "midpoint" and "heun"."""
+
+    METHODS = {"cf4": 0, "midpoint": 1, "heun": 2}
 
     def __init__(self, terms: Sequence[Term], spin: float = 1, rotating_frame: bool = True,
-                 n_squares: int = 24, device: str = "cuda"):
+                 n_squares: int = 24, method: str = "cf4", device: str = "cuda"):
         if spin not in (0.5, 1, 1.0):
             raise ValueError("spin must be 0.5 or 1")
+        if method not in self.METHODS:
+            raise ValueError(f"method must be one of {sorted(self.METHODS)}")
+        self.method = self.METHODS[method]
         self.spin_twice = 1 if spin == 0.5 else 2
         self.terms: List[Term] = list(terms)
         self.rotating_frame = bool(rotating_frame)
@@ -64,7 +79,8 @@ class Simulator:
         K, L = grid_from_times(t_start, t_end, dt_integration, dt_output)
         return Problem(self.spin_twice, self.terms, float(t_start), float(dt_output), K, L,
                        self.n_squares, self.rotating_frame,
-                       params=np.zeros(0) if params is None else params, psi0=psi0)
+                       params=np.zeros(0) if params is None else params, psi0=psi0,
+                       method=self.method)
 
     def evaluate(self, psi0, t_start: float, t_end: float, dt_integration: float,
                  dt_output: float, params=None, keep_operators: bool = True,

@@ -43,6 +43,9 @@ import numpy as np
 CONST, COS, SIN, PWC, PWC_COS, PWC_SIN = 0, 1, 2, 3, 4, 5
 # field components
 X, Y, Z, Q = 0, 1, 2, 3
+# integration methods: commutator-free fourth-order Magnus (the solver's), and
+# the two Euler-family sampling methods the paper compares it with
+CF4, MIDPOINT, HEUN = 0, 1, 2
 
 INF = float("inf")
 
@@ -81,6 +84,7 @@ class Problem:
     params: np.ndarray = field(default_factory=lambda: np.zeros(0))
     psi0: Optional[np.ndarray] = None
     name: str = ""
+    method: int = CF4
 
     def __post_init__(self):
         self.params = np.ascontiguousarray(np.asarray(self.params, dtype=np.float64))

@@ -1,0 +1,110 @@
+"""Parity at the full sizes of the batched, serving and control workloads,
+on outputs the oracle can compute one simulation at a time."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2204_05586_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_batched_sensing_full(torch_dev, oracle):
+    """All 4096 uneven spin-1 simulations (4.5e9 CF4 steps) in one batch,
+    states only, autotuned launch; the longest, the shortest and 4 seeded
+    simulations against the oracle."""
+    import torch
+    from paper_2204_05586_amd import autotune, native
+    probs = W.batched_sensing(seed=2)
+    opts = autotune.tune(probs, cache_path=None, reps=2)
+    plan = native.BatchPlan(probs, **opts)
+    bufs = plan.allocate(store_u=False)
+    print(f"[gpu] full batched sensing {plan.info()} options {opts}", flush=True)
+    plan.run(bufs)
+    torch.cuda.synchronize()
+    ks = np.array([p.n_samples for p in probs])
+    rng = np.random.default_rng(2024)
+    pick = sorted({int(ks.argmax()), int(ks.argmin()), *rng.choice(len(probs), 4, replace=False)})
+    for i in pick:
+        ref = oracle.solve(probs[i])
+        got = plan.split(bufs, i)
+        d = max(np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"])),
+                np.max(np.abs(got["psi_final"].cpu().numpy() - ref["psi_final"])))
+        print(f"sim {i} K={probs[i].n_samples}: max |d| = {d:.3e}", flush=True)
+        assert d <= TOL, (i, d)
+    plan.close()
+
+
+def test_serving_stream_full(torch_dev, oracle):
+    """A seeded 200-request Poisson stream at 1000 req/s (30 % spin-1/2,
+    K log-uniform in [1e3, 1e6]) submitted on schedule: every result equals
+    the same simulation run alone, every tenth is checked against the
+    oracle, and latencies are reported."""
+    import torch
+    from paper_2204_05586_amd import native
+    stream = W.serving_stream(1000.0, n_requests=200, rate_index=4)
+    srv = native.Server()
+    base = srv.clock() + 0.05
+    tickets = []
+    for r in stream:
+        delay = base + r.arrival - srv.clock()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(r.problem))
+    lat, worst = [], 0.0
+    for j, (t, r) in enumerate(zip(tickets, stream)):
+        info = srv.wait(t, 300.0)
+        lat.append(info["t_done"] - (base + r.arrival))
+        p = r.problem
+        got = srv.fetch(t, p)
+        K, N = p.n_samples, p.dim
+        U = torch.empty((K, N, N), dtype=torch.complex128, device="cuda")
+        psi = torch.empty((K, N), dtype=torch.complex128, device="cuda")
+        fin = torch.empty((N,), dtype=torch.complex128, device="cuda")
+        ws = native.alloc_workspace(native.propagate_workspace_size(p.spin_twice, K))
+        native.integrate(p, native.device_params(p), U, launch=(1, 256))
+        native.propagate(p.spin_twice, U, native.device_state(p.psi0), psi, fin, ws)
+        torch.cuda.synchronize()
+        d = float((got["psi"] - psi).abs().max())
+        worst = max(worst, d)
+        assert d <= 1e-13, (j, d)
+        if j % 10 == 0:
+            ref = oracle.solve(p)
+            assert np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"])) <= TOL, j
+        srv.release(t)
+        del U, psi, ws
+    lat = np.array(lat) * 1e3
+    print(f"served 200: max |d| vs alone {worst:.3e}; latency p50 {np.percentile(lat, 50):.3f} ms "
+          f"p99 {np.percentile(lat, 99):.3f} ms", flush=True)
+    srv.close()
+
+
+def test_control_gradients_full(torch_dev, oracle):
+    """All 1024 control instances (512 gradients each); three seeded
+    instances against the oracle's adjoint."""
+    import torch
+    from paper_2204_05586_amd import native
+    probs = W.control_batch(seed=4)
+    plan = native.AdjointPlan(probs, 1)
+    bufs = plan.allocate()
+    print(f"[gpu] full control gradients n={len(probs)}", flush=True)
+    plan.run(bufs)
+    torch.cuda.synchronize()
+    loss = bufs["loss"].cpu().numpy()
+    for i in (0, 511, 1023):
+        l_ref, g_ref = oracle.adjoint_population(probs[i], 1)
+        g = plan.grad_of(bufs, i).cpu().numpy()
+        r = float(np.max(np.abs(g - g_ref)) / np.max(np.abs(g_ref)))
+        print(f"instance {i}: loss {loss[i]:.6f} rel grad err {r:.2e}", flush=True)
+        assert abs(loss[i] - l_ref) <= 1e-11 and r <= 1e-9
+    plan.close()

@@ -156,3 +156,29 @@ def test_simulator_front_end(dev, oracle):
     assert res.state.shape == (2000, 3)
     assert np.max(np.abs(res.state.cpu().numpy() - ref["psi"])) <= TOL
     assert np.max(np.abs(res.time_evolution.cpu().numpy() - ref["U"])) <= TOL
+
+
+def test_spin_projection(dev, oracle):
+    """<J> of the GPU states vs the oracle's <J> of the oracle's states, and
+    the projection kernel alone on identical inputs."""
+    import torch
+    from paper_2204_05586_amd import Simulator, native
+    sim = Simulator(W.neural_pulse_terms(), spin=1, rotating_frame=True, n_squares=28)
+    res = sim.evaluate([0.6, 0.8j, 0], 0.0495, 0.0505, 5e-8, 5e-7)
+    prob = sim.problem(0.0495, 0.0505, 5e-8, 5e-7, psi0=[0.6, 0.8j, 0])
+    ref = oracle.solve(prob)
+    J = res.spin.cpu().numpy()
+    assert np.max(np.abs(J - oracle.spin_projection(ref["psi"]))) <= TOL
+    for N in (2, 3):
+        rng = np.random.default_rng(N)
+        psi = rng.normal(size=(1001, N)) + 1j * rng.normal(size=(1001, N))
+        got = native.spin_projection(torch.from_numpy(psi).cuda()).cpu().numpy()
+        assert np.max(np.abs(got - oracle.spin_projection(psi))) < 1e-14
+
+
+@pytest.mark.parametrize("method", [W.MIDPOINT, W.HEUN])
+@pytest.mark.parametrize("spin_twice,frame", [(1, True), (2, True), (2, False)])
+def test_euler_methods(dev, oracle, method, spin_twice, frame):
+    rng = np.random.default_rng(50 + method + 10 * spin_twice + frame)
+    prob = W.random_problem(rng, spin_twice, 777, 5, rotating_frame=frame).replace(method=method)
+    _compare(_gpu(prob), oracle.solve(prob, want_U=True), name=f"method={method}")
