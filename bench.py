@@ -33,16 +33,25 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # passes, calibrated against a 1 GiB copy (FETCH x 2.000, WRITE x 1.000), keyed by
 # the hash of the kernel sources it was taken with: reported only while the
 # sources are unchanged.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("batch_integrate_kernel", "batched_sensing"): {
+        "src": "4bd4814015d23db4",
+        "fetch_kib": 3573.875, "write_kib": 64050200.125,
+        "bytes": int(round((3573.875 * 2.000 + 64050200.125 * 1.000) * 1024)),
+    },
+}
+
+
+# sources that define the batched integrator (work_integrate_kernel)
+INTEGRATOR_SOURCES = ("mss_device.h", "mss_internal.h", "mss_work.h", "mss_work.hip")
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2204_05586_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + f.read())
+    for name in INTEGRATOR_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 
@@ -281,7 +290,8 @@ def main():
         tau = problems[0].n_squares
         res = bench_batched(problems, args.steps, args.warmup, args.graph_reps, not args.no_tune)
         kernel = "batch_integrate_kernel"
-        plain = bench_plain(W.spin_one_sensing(), args.plain_steps, 3)
+        plain = (bench_plain(W.spin_one_sensing(), args.plain_steps, 3)
+                 if args.plain_steps > 0 else None)
         value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
             res["fine_steps"]
         config = {"workload": f"batched_sensing: {len(problems)} spin-1 simulations, seed 2, "
@@ -295,9 +305,9 @@ def main():
         extra = {"integrate_ms_mean": round(integ_ms, 3),
                  "propagate_ms_mean": round(res["propagate_ms"], 3),
                  "graph_ms_per_step": round(res.get("graph_ms_per_step", 0.0), 3) or None,
-                 "plain": {k: (round(v, 4) if isinstance(v, float) else v)
-                           for k, v in plain.items()},
-                 "batched_over_plain": round(value / plain["value"], 3)}
+                 "plain": ({k: (round(v, 4) if isinstance(v, float) else v)
+                            for k, v in plain.items()} if plain else None),
+                 "batched_over_plain": round(value / plain["value"], 3) if plain else None}
         base_problems = problems
     else:
         prob = W.spin_one_sensing() if args.workload == "spin_one_sensing" else W.spin_half_rabi()
