@@ -184,6 +184,56 @@ mss_status mss_solve(const mss_problem* p, const double* params, const double* p
                      double* psi, double* psi_final, double* time, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* ---- user field samplers ------------------------------------------------
+ * A field function written by the user in HIP C++, compiled at run time
+ * (hiprtc) into its own integrator: the counterpart of the paper's user
+ * field function compiled into the integrator (Sec. "Compilation of
+ * integrator"), for fields the term kinds cannot express.  The source
+ * defines
+ *
+ *   __device__ void mss_user_field(double t, const double* params, double* field);
+ *
+ * which receives field[0..3] zeroed and sets f_x, f_y, f_z, f_q in Hz at
+ * time t (s); f_q is ignored for spin-1/2.  params is the device parameter
+ * vector passed to mss_sampler_integrate (NULL when n_params == 0).  The
+ * source is compiled after the library's device header, so namespace mss
+ * (e.g. mss::sincos_cw, accurate for phases up to 1.5e6 rad) and the device
+ * math library are available; flags: gfx950, -O3, C++17, fused multiply-add
+ * contraction as hipcc's default (put `#pragma clang fp contract(off)` in
+ * the function to fix its evaluation order).  The code must be safe to run
+ * by every lane: it must read params within n_params and write only
+ * field[0..3]. */
+typedef struct mss_sampler_s* mss_sampler;
+
+/* Compile `source` (NUL-terminated) with n_options extra compiler options
+ * (options may be NULL when n_options == 0, e.g. "-DAMP=2.0").  Host only:
+ * no GPU is needed.  On success *out owns the compiled code object.  A
+ * compile error returns MSS_E_INVALID with the compiler log in
+ * mss_last_error() and *out = NULL. */
+mss_status mss_sampler_create(const char* source, const char* const* options, int32_t n_options,
+                              mss_sampler* out);
+
+/* Compiler log of a successful compile (warnings; "" if none).  Owned by
+ * the sampler, valid until mss_sampler_destroy. */
+const char* mss_sampler_log(mss_sampler s);
+
+/* Interval operators U_k of `p` with the field from the sampler, as
+ * mss_integrate (same outputs, launch shapes and errors).  p->n_terms must
+ * be 0.  The code object is loaded on the current device at its first use
+ * there (MSS_E_DEVICE if loading fails).  Thread-safe. */
+mss_status mss_sampler_integrate(mss_sampler s, const mss_problem* p, const double* params,
+                                 double* U, double* time, const mss_launch* launch, void* stream);
+
+/* Whole path with a sampler: mss_sampler_integrate then mss_propagate, with
+ * the workspace of mss_solve (mss_workspace_size). */
+mss_status mss_sampler_solve(mss_sampler s, const mss_problem* p, const double* params,
+                             const double* psi0, double* U, double* psi, double* psi_final,
+                             double* time, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronise every device the sampler was loaded on, unload it there and
+ * free it.  NULL is a no-op. */
+void mss_sampler_destroy(mss_sampler s);
+
 /* ---- batches ------------------------------------------------------------
  * Many independent simulations (uneven K, mixed spin allowed) in one
  * persistent integrator launch and one segmented scan.  Sweeps over

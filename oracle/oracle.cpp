@@ -56,6 +56,12 @@ struct OTerm {
   double seg_t0, seg_len;
 };
 
+// A field function supplied by the caller instead of terms, with the
+// paper's calling convention for the user's field function (Sec.
+// "Compilation of integrator"): time, sweep parameters, and the field
+// sample f_x, f_y, f_z, f_q (Hz) to fill.  Double precision only.
+typedef void (*OFieldFn)(double t, const double* params, double* field);
+
 struct OProblem {
   int32_t spin_twice;  // 1: spin-1/2, 2: spin-1
   int32_t n_terms;
@@ -68,6 +74,7 @@ struct OProblem {
   double t_start;
   double dt_out;       // Dt
   const OTerm* terms;
+  OFieldFn field_fn;   // non-null: the field comes from this function, terms unused
 };
 
 enum { K_CONST = 0, K_COS = 1, K_SIN = 2, K_PWC = 3, K_PWC_COS = 4, K_PWC_SIN = 5 };
@@ -111,10 +118,22 @@ int64_t segment(const OTerm& tm, R t) {
   return s;
 }
 
+// The caller's field function (double only: the entry points refuse a field
+// function for other number types).
+inline void call_field_fn(const OProblem& p, const double* params, double t, double out[4]) {
+  p.field_fn(t, params, out);
+}
+template <class R>
+void call_field_fn(const OProblem&, const R*, R, R*) {}
+
 // Field functions f_j(t) in Hz, j = x, y, z, q.  Terms are summed in list order.
 template <class R>
 void field(const OProblem& p, const R* params, R t, R out[4]) {
   for (int j = 0; j < 4; ++j) out[j] = R(0);
+  if (p.field_fn) {
+    call_field_fn(p, params, t, out);
+    return;
+  }
   for (int i = 0; i < p.n_terms; ++i) {
     const OTerm& tm = p.terms[i];
     if (!(R(tm.t_on) < t && t < R(tm.t_off))) continue;
@@ -713,11 +732,12 @@ int oracle_spin_projection(int spin_twice, int64_t K, const double* psi, double*
 
 // loss = |psi_final[m]|^2 and grad[q] = dloss/dparams[q] for q < n_params.
 // Returns 1 on bad arguments, 2 if a z or q term uses a parameter slot, 3 for
-// a method other than CF4.
+// a method other than CF4, 4 for a field function (no parameter derivatives).
 int oracle_adjoint_population(const OProblem* p, const double* params, const double* psi0, int m,
                               double* loss, double* grad) {
   if (!p || p->n_samples < 1 || p->n_fine < 1 || m < 0 || m > p->spin_twice) return 1;
   if (p->method != 0) return 3;
+  if (p->field_fn) return 4;
   for (int i = 0; i < p->n_terms; ++i) {
     const OTerm& t = p->terms[i];
     const bool slots = t.a_slot >= 0 || t.f_slot >= 0 || t.phi_slot >= 0 || t.seg_a_slot >= 0 ||
@@ -738,6 +758,7 @@ int oracle_solve(const OProblem* p, const double* params, const double* psi0, do
 // differences whose step must sit far above the rounding floor.
 int oracle_solve_ld(const OProblem* p, const long double* params, const long double* psi0,
                     long double* psi_final) {
+  if (p && p->field_fn) return 4;
   return solve<long double>(p, params, psi0, nullptr, nullptr, psi_final);
 }
 

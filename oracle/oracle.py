@@ -50,7 +50,35 @@ class _Problem(C.Structure):
     _fields_ = [("spin_twice", C.c_int32), ("n_terms", C.c_int32), ("n_fine", C.c_int32),
                 ("n_squares", C.c_int32), ("rotating_frame", C.c_int32), ("n_params", C.c_int32),
                 ("method", C.c_int32), ("n_samples", C.c_int64), ("t_start", C.c_double), ("dt_out", C.c_double),
-                ("terms", C.POINTER(_Term))]
+                ("terms", C.POINTER(_Term)), ("field_fn", C.c_void_p)]
+
+
+# field function callback: (t, params, field[4]) with the paper's calling
+# convention for a user field function
+_FIELD_FN = C.CFUNCTYPE(None, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double))
+
+
+class _FieldFn:
+    """A Python field function fn(t, params, field) (field: float64 [4] to
+    fill with f_x, f_y, f_z, f_q in Hz) as a C callback.  Exceptions raised
+    inside are kept and re-raised after the oracle call returns."""
+
+    def __init__(self, fn, n_params: int):
+        self.error = None
+
+        def cb(t, p, out):
+            try:
+                params = np.ctypeslib.as_array(p, shape=(max(n_params, 1),))[:n_params]
+                fn(float(t), params, np.ctypeslib.as_array(out, shape=(4,)))
+            except BaseException as e:  # noqa: BLE001 - re-raised by check()
+                if self.error is None:
+                    self.error = e
+
+        self.c = _FIELD_FN(cb)
+
+    def check(self):
+        if self.error is not None:
+            raise self.error
 
 
 _lib = None
@@ -93,8 +121,10 @@ def _dp(a: np.ndarray):
 class _Packed:
     """Keeps the ctypes problem and its term array alive together."""
 
-    def __init__(self, prob):
+    def __init__(self, prob, field_fn=None):
         terms = list(prob.terms)
+        if field_fn is not None and terms:
+            raise ValueError("a problem with a field function carries no terms")
         arr = (_Term * max(1, len(terms)))()
         for i, t in enumerate(terms):
             arr[i] = _Term(int(t.kind), int(t.comp), int(t.a_slot), int(t.f_slot),
@@ -108,7 +138,25 @@ class _Packed:
                           int(bool(prob.rotating_frame)), int(params.size),
                           int(getattr(prob, "method", 0)), int(prob.n_samples),
                           float(prob.t_start), float(prob.dt_out), arr)
+        self.fn = None
+        if field_fn is not None:
+            self.fn = _FieldFn(field_fn, int(params.size))
+            self.p.field_fn = C.cast(self.fn.c, C.c_void_p)
         self.dim = int(prob.spin_twice) + 1
+
+    def call(self, f, *args):
+        """Run oracle entry point f; a field function runs single-threaded
+        (it holds the interpreter lock anyway) and its errors propagate."""
+        if self.fn is None:
+            return f(*args)
+        n = get_threads()
+        set_threads(1)
+        try:
+            rc = f(*args)
+        finally:
+            set_threads(n)
+        self.fn.check()
+        return rc
 
 
 def set_threads(n: int) -> None:
@@ -119,11 +167,11 @@ def get_threads() -> int:
     return lib().oracle_get_threads()
 
 
-def field(prob, t: float) -> np.ndarray:
+def field(prob, t: float, field_fn=None) -> np.ndarray:
     """Field functions (f_x, f_y, f_z, f_q) in Hz at time t."""
-    pk = _Packed(prob)
+    pk = _Packed(prob, field_fn)
     out = np.zeros(4)
-    lib().oracle_field(C.byref(pk.p), _dp(pk.params), float(t), _dp(out))
+    pk.call(lib().oracle_field, C.byref(pk.p), _dp(pk.params), float(t), _dp(out))
     return out
 
 
@@ -155,14 +203,14 @@ def lie_trotter_residual(theta, tau: int) -> np.ndarray:
     return _cmat(out, 3).copy()
 
 
-def operators(prob, k0: int = 0, count: int | None = None) -> np.ndarray:
+def operators(prob, k0: int = 0, count: int | None = None, field_fn=None) -> np.ndarray:
     """U_k for k in [k0, k0 + count), shape [count, N, N] complex128."""
-    pk = _Packed(prob)
+    pk = _Packed(prob, field_fn)
     if count is None:
         count = int(prob.n_samples) - k0
     U = np.zeros((count, pk.dim, pk.dim), dtype=np.complex128)
-    rc = lib().oracle_operators(C.byref(pk.p), _dp(pk.params), int(k0), int(count),
-                                _dp(U.view(np.float64)))
+    rc = pk.call(lib().oracle_operators, C.byref(pk.p), _dp(pk.params), int(k0), int(count),
+                 _dp(U.view(np.float64)))
     if rc:
         raise ValueError("oracle_operators: bad arguments")
     return U
@@ -181,17 +229,18 @@ def states(U: np.ndarray, psi0) -> tuple[np.ndarray, np.ndarray]:
     return psi, fin
 
 
-def solve(prob, want_U: bool = False) -> dict:
-    """Full solve: operators U_k, states psi_k (k < K) and psi_final."""
-    pk = _Packed(prob)
+def solve(prob, want_U: bool = False, field_fn=None) -> dict:
+    """Full solve: operators U_k, states psi_k (k < K) and psi_final.
+    field_fn(t, params, field) replaces the problem's terms when given."""
+    pk = _Packed(prob, field_fn)
     K, N = int(prob.n_samples), pk.dim
     v0 = np.ascontiguousarray(np.asarray(prob.psi0, dtype=np.complex128))
     psi = np.zeros((K, N), dtype=np.complex128)
     fin = np.zeros(N, dtype=np.complex128)
     U = np.zeros((K, N, N), dtype=np.complex128) if want_U else None
-    rc = lib().oracle_solve(C.byref(pk.p), _dp(pk.params), _dp(v0.view(np.float64)),
-                            _dp(U.view(np.float64)) if U is not None else None,
-                            _dp(psi.view(np.float64)), _dp(fin.view(np.float64)))
+    rc = pk.call(lib().oracle_solve, C.byref(pk.p), _dp(pk.params), _dp(v0.view(np.float64)),
+                 _dp(U.view(np.float64)) if U is not None else None,
+                 _dp(psi.view(np.float64)), _dp(fin.view(np.float64)))
     if rc:
         raise ValueError("oracle_solve: bad arguments")
     return {"U": U, "psi": psi, "psi_final": fin}

@@ -28,6 +28,11 @@ mss_status api_fail(mss_status s, const char* fmt, ...) {
   return s;
 }
 
+mss_status api_fail_text(mss_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
 mss_status api_ok() {
   g_err.clear();
   return MSS_OK;
@@ -211,6 +216,12 @@ mss_status resolve_launch(const mss_problem* p, const mss_launch* in, int* slice
 
 }  // namespace
 
+namespace mss {
+mss_status api_resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block) {
+  return resolve_launch(p, in, slices, block);
+}
+}  // namespace mss
+
 extern "C" {
 
 const char* mss_status_str(mss_status s) {
@@ -277,18 +288,18 @@ mss_status mss_integrate(const mss_problem* p, const double* params, double* U, 
   memset(&a, 0, sizeof a);
   a.fp.n_terms = p->n_terms;
   for (int i = 0; i < p->n_terms; ++i) a.fp.t[i] = p->terms[i];
-  a.params = params;
-  a.U = U;
-  a.time = time;
-  a.t_start = p->t_start;
-  a.dt_out = p->dt_out;
-  a.dt = p->dt_out / (double)p->n_fine;
-  a.K = p->n_samples;
-  a.L = p->n_fine;
-  a.tau = p->spin_twice == 2 ? p->n_squares : 0;
-  a.frame = p->rotating_frame;
-  a.method = p->method;
-  a.slices_log2 = ilog2(S);
+  a.g.params = params;
+  a.g.U = U;
+  a.g.time = time;
+  a.g.t_start = p->t_start;
+  a.g.dt_out = p->dt_out;
+  a.g.dt = p->dt_out / (double)p->n_fine;
+  a.g.K = p->n_samples;
+  a.g.L = p->n_fine;
+  a.g.tau = p->spin_twice == 2 ? p->n_squares : 0;
+  a.g.frame = p->rotating_frame;
+  a.g.method = p->method;
+  a.g.slices_log2 = ilog2(S);
   hipError_t e = launch_integrate(p->spin_twice + 1, a, B, (hipStream_t)stream);
   if (e != hipSuccess) return api_hip_fail(e, "integrate launch");
   return api_ok();

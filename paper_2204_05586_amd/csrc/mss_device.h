@@ -520,4 +520,43 @@ __device__ __forceinline__ void interval_operator(const Terms& terms, const doub
   *tk_out = tk;
 }
 
+// Time grid, outputs and options of one simulation's integrator launch
+// (everything but the field source).
+struct IntervalGrid {
+  const double* params;  // the simulation's parameter vector (may be null)
+  double* U;             // [K][N][N] complex
+  double* time;          // [K] interval start times, or null
+  double t_start;
+  double dt_out;         // Dt
+  double dt;             // Dt / L
+  int64_t K;
+  int32_t L;
+  int32_t tau;
+  int32_t frame;
+  int32_t slices_log2;
+  int32_t method;
+  int32_t pad;
+};
+
+// Lane body of the single-simulation integrator: one lane per (interval k,
+// slice s), the S = 2^slices_log2 slices of an interval in consecutive
+// lanes of one wave; the whole wave must call it.  `terms` is any field
+// source field_eval accepts.
+template <int N, class Terms>
+__device__ __forceinline__ void integrate_lanes(const Terms& terms, const IntervalGrid& g) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = g.slices_log2;
+  const int64_t k = gid >> sl;
+  const int s = (int)(gid & ((1 << sl) - 1));
+  const bool active = k < g.K;
+  Mat<N> U;
+  double tk;
+  interval_operator<N>(terms, g.params, g.t_start, g.dt_out, g.dt, g.L, g.tau, g.frame, g.method,
+                       k, s, sl, active, U, &tk);
+  if (active && s == 0) {
+    store_mat<N>(g.U + (size_t)k * 2 * N * N, U);
+    if (g.time) g.time[k] = tk;
+  }
+}
+
 }  // namespace mss

@@ -16,22 +16,12 @@ constexpr int kScanTile = 64 * kScanPerLane;
 
 struct IntegrateArgs {
   FieldProgram fp;
-  const double* params;
-  double* U;
-  double* time;
-  double t_start;
-  double dt_out;  // Dt
-  double dt;      // Dt / L
-  int64_t K;
-  int32_t L;
-  int32_t tau;
-  int32_t frame;
-  int32_t slices_log2;
-  int32_t method;
+  IntervalGrid g;
 };
 
 // host helpers shared by the C-ABI translation units (mss_api.hip)
 mss_status api_fail(mss_status s, const char* fmt, ...);
+mss_status api_fail_text(mss_status s, const std::string& msg);
 mss_status api_ok();
 mss_status api_hip_fail(hipError_t e, const char* what);
 std::string api_last_error_copy();
@@ -39,6 +29,8 @@ mss_status api_validate_problem(const mss_problem* p);
 int api_device_cu_count();
 int api_plan_slices(int64_t K, int32_t L, int cu);
 int api_ilog2(int x);
+// launch shape (lane-slices per interval, block size) of one simulation
+mss_status api_resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block);
 
 hipError_t launch_integrate(int N, const IntegrateArgs& a, int block, hipStream_t st);
 hipError_t launch_scan_reduce(int N, const double* M, int64_t n, double* agg, hipStream_t st);

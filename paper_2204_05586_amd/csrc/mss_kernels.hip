@@ -9,25 +9,12 @@
 
 namespace mss {
 
-// One lane per (interval k, slice s).  The S = 2^slices_log2 slices of an
-// interval sit in consecutive lanes of one wave; slice s integrates fine
-// steps [s L / S, (s + 1) L / S) and the partial products are combined in
-// order (later slices on the left) with wave shuffles.
+// One lane per (interval k, slice s); slice s integrates fine steps
+// [s L / S, (s + 1) L / S) and the partial products are combined in order
+// (later slices on the left) with wave shuffles.
 template <int N>
 __global__ void __launch_bounds__(256) integrate_kernel(const IntegrateArgs A) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int sl = A.slices_log2;
-  const int64_t k = gid >> sl;
-  const int s = (int)(gid & ((1 << sl) - 1));
-  const bool active = k < A.K;
-  Mat<N> U;
-  double tk;
-  interval_operator<N>(ArgTerms{A.fp}, A.params, A.t_start, A.dt_out, A.dt, A.L, A.tau, A.frame,
-                       A.method, k, s, sl, active, U, &tk);
-  if (active && s == 0) {
-    store_mat<N>(A.U + (size_t)k * 2 * N * N, U);
-    if (A.time) A.time[k] = tk;
-  }
+  integrate_lanes<N>(ArgTerms{A.fp}, A.g);
 }
 
 template <int N>
@@ -86,7 +73,7 @@ __global__ void __launch_bounds__(256) spin_projection_kernel(const double* __re
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_integrate(int N, const IntegrateArgs& a, int block, hipStream_t st) {
-  const int64_t lanes = a.K << a.slices_log2;
+  const int64_t lanes = a.g.K << a.g.slices_log2;
   const int64_t grid = (lanes + block - 1) / block;
   if (N == 2)
     hipLaunchKernelGGL(integrate_kernel<2>, dim3((unsigned)grid), dim3(block), 0, st, a);

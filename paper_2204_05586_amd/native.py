@@ -31,7 +31,8 @@ EXPORTS = [
     "mss_server_wait", "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
     "mss_server_clock", "mss_server_destroy", "mss_adjoint_plan_create",
     "mss_adjoint_workspace_size", "mss_adjoint_param_count", "mss_adjoint_run",
-    "mss_adjoint_plan_destroy",
+    "mss_adjoint_plan_destroy", "mss_sampler_create", "mss_sampler_log", "mss_sampler_integrate",
+    "mss_sampler_solve", "mss_sampler_destroy",
 ]
 
 MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
@@ -152,6 +153,14 @@ def lib() -> C.CDLL:
         L.mss_adjoint_plan_destroy.restype = None
         L.mss_batch_plan_destroy.argtypes = [vp]
         L.mss_batch_plan_destroy.restype = None
+        L.mss_sampler_create.argtypes = [C.c_char_p, C.POINTER(C.c_char_p), C.c_int32,
+                                         C.POINTER(vp)]
+        L.mss_sampler_log.argtypes = [vp]
+        L.mss_sampler_log.restype = C.c_char_p
+        L.mss_sampler_integrate.argtypes = [vp, PP, vp, vp, vp, C.POINTER(Launch), vp]
+        L.mss_sampler_solve.argtypes = [vp, PP, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_sampler_destroy.argtypes = [vp]
+        L.mss_sampler_destroy.restype = None
         for name in ("mss_validate", "mss_plan_launch", "mss_workspace_size",
                      "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
                      "mss_solve", "mss_spin_projection", "mss_batch_plan_create", "mss_batch_layout",
@@ -160,7 +169,8 @@ def lib() -> C.CDLL:
                      "mss_server_submit", "mss_server_poll", "mss_server_wait",
                      "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
                      "mss_adjoint_plan_create", "mss_adjoint_workspace_size",
-                     "mss_adjoint_param_count", "mss_adjoint_run"):
+                     "mss_adjoint_param_count", "mss_adjoint_run", "mss_sampler_create",
+                     "mss_sampler_integrate", "mss_sampler_solve"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -292,10 +302,10 @@ def spin_projection(psi, stream=None):
 
 
 def solve(prob, store_u: bool = False, want_time: bool = False, device="cuda",
-          stream=None) -> dict:
-    """Allocate outputs on the device and run the whole path (mss_solve).
-    Returns torch tensors: psi [K, N], psi_final [N], U [K, N, N] or None,
-    time [K] or None."""
+          stream=None, sampler: "Optional[Sampler]" = None) -> dict:
+    """Allocate outputs on the device and run the whole path (mss_solve, or
+    mss_sampler_solve when a sampler supplies the field).  Returns torch
+    tensors: psi [K, N], psi_final [N], U [K, N, N] or None, time [K] or None."""
     import torch
     K, N = int(prob.n_samples), int(prob.spin_twice) + 1
     params = device_params(prob, device)
@@ -305,8 +315,59 @@ def solve(prob, store_u: bool = False, want_time: bool = False, device="cuda",
     U = torch.empty((K, N, N), dtype=torch.complex128, device=device) if store_u else None
     time = torch.empty((K,), dtype=torch.float64, device=device) if want_time else None
     ws = alloc_workspace(workspace_size(prob, store_u), device)
-    solve_into(prob, params, psi0, psi, fin, U, time, ws, stream)
+    if sampler is None:
+        solve_into(prob, params, psi0, psi, fin, U, time, ws, stream)
+    else:
+        sampler.solve_into(prob, params, psi0, psi, fin, U, time, ws, stream)
     return {"psi": psi, "psi_final": fin, "U": U, "time": time}
+
+
+# ---- user field samplers ---------------------------------------------------
+
+class Sampler:
+    """A user field function in HIP C++, compiled at run time (hiprtc) into
+    its own integrator (mss_sampler_create).  ``source`` defines
+    ``__device__ void mss_user_field(double t, const double* params,
+    double* field)`` setting f_x, f_y, f_z, f_q in Hz; problems solved with
+    it carry no terms.  Compilation needs no GPU."""
+
+    def __init__(self, source: str, options=()):
+        opts = [str(o).encode() for o in options]
+        arr = (C.c_char_p * max(1, len(opts)))(*opts) if opts else None
+        h = C.c_void_p()
+        check(lib().mss_sampler_create(source.encode(), arr, len(opts), C.byref(h)))
+        self._h = h
+        self.source = source
+
+    @property
+    def log(self) -> str:
+        return lib().mss_sampler_log(self._h).decode()
+
+    def integrate(self, prob, params, U, time=None, launch: Optional[tuple[int, int]] = None,
+                  stream=None) -> None:
+        pk = PackedProblem(prob)
+        ln = C.byref(Launch(*launch)) if launch else None
+        check(lib().mss_sampler_integrate(self._h, pk.ref, _ptr(params), _ptr(U), _ptr(time), ln,
+                                          _stream(stream)))
+
+    def solve_into(self, prob, params, psi0, psi, psi_final=None, U=None, time=None, ws=None,
+                   stream=None) -> None:
+        pk = PackedProblem(prob)
+        nbytes = 0 if ws is None else int(ws.numel() * ws.element_size())
+        check(lib().mss_sampler_solve(self._h, pk.ref, _ptr(params), _ptr(psi0), _ptr(U),
+                                      _ptr(psi), _ptr(psi_final), _ptr(time), _ptr(ws), nbytes,
+                                      _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().mss_sampler_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- batches ---------------------------------------------------------------

@@ -4,8 +4,11 @@ rotating frame, squaring count) and reused across ``evaluate`` calls with
 different sweep parameters, returning ``Results`` (time, state, time
 evolution operators).
 
-Field functions are field programs (lists of ``workloads.Term``) instead of
-compiled Python functions; ``params`` plays the role of sweep_parameters.
+The field is either a field program (a list of ``workloads.Term``,
+interpreted by the precompiled integrator) or, like the paper's user field
+function, code: HIP source defining ``mss_user_field(t, params, field)``,
+compiled at run time into its own integrator (``native.Sampler``).
+``params`` plays the role of sweep_parameters.
 """
 from __future__ import annotations
 
@@ -55,21 +58,30 @@ def grid_from_times(t_start: float, t_end: float, dt_integration: float, dt_outp
 class Simulator:
     """Spin-1/2 or spin-1 solver configured once, evaluated many times.
 
-    spin: 0.5 or 1.  terms: field program.  rotating_frame: per-interval
+    spin: 0.5 or 1.  terms: field program, or HIP source of a field function
+    (str), or a compiled ``native.Sampler``; sampler_options: extra compiler
+    options for a source.  rotating_frame: per-interval
     rotating frame (paper default: on).  n_squares: Lie-Trotter squaring
     count tau for spin-1 (paper default 24).  method: "cf4" (default), or
     the Euler-family comparison samplings "midpoint" and "heun"."""
 
     METHODS = {"cf4": 0, "midpoint": 1, "heun": 2}
 
-    def __init__(self, terms: Sequence[Term], spin: float = 1, rotating_frame: bool = True,
-                 n_squares: int = 24, method: str = "cf4", device: str = "cuda"):
+    def __init__(self, terms, spin: float = 1, rotating_frame: bool = True,
+                 n_squares: int = 24, method: str = "cf4", device: str = "cuda",
+                 sampler_options: Sequence[str] = ()):
         if spin not in (0.5, 1, 1.0):
             raise ValueError("spin must be 0.5 or 1")
         if method not in self.METHODS:
             raise ValueError(f"method must be one of {sorted(self.METHODS)}")
         self.method = self.METHODS[method]
         self.spin_twice = 1 if spin == 0.5 else 2
+        self.sampler: Optional[native.Sampler] = None
+        if isinstance(terms, str):
+            self.sampler = native.Sampler(terms, sampler_options)
+            terms = []
+        elif isinstance(terms, native.Sampler):
+            self.sampler, terms = terms, []
         self.terms: List[Term] = list(terms)
         self.rotating_frame = bool(rotating_frame)
         self.n_squares = int(n_squares)
@@ -88,5 +100,5 @@ class Simulator:
         prob = self.problem(t_start, t_end, dt_integration, dt_output, params, psi0)
         native.validate(prob)
         r = native.solve(prob, store_u=keep_operators, want_time=True, device=self.device,
-                         stream=stream)
+                         stream=stream, sampler=self.sampler)
         return Results(r["time"], r["psi"], r["U"], r["psi_final"])

@@ -94,3 +94,47 @@ def test_solve_requires_buffers():
     st = native.lib().mss_solve(pk.ref, None, None, None, None, None, None, None, 0, None)
     assert st == native.MSS_E_INVALID
     assert "psi0" in native.last_error()
+
+
+# ---- user field samplers (compiled at run time; needs no GPU) ---------------
+
+def test_sampler_compiles_without_gpu():
+    from tests import user_fields as F
+    s = native.Sampler(F.CHIRP_SOURCE)
+    assert isinstance(s.log, str)
+    s.close()
+    s.close()  # idempotent
+
+
+def test_sampler_options_are_passed():
+    src = "#ifndef AMP\n#error AMP undefined\n#endif\n" \
+          "__device__ void mss_user_field(double t, const double* p, double* f) { f[0] = AMP; }\n"
+    with pytest.raises(native.MssError, match="AMP undefined"):
+        native.Sampler(src)
+    native.Sampler(src, options=["-DAMP=2.0"]).close()
+
+
+def test_sampler_compile_errors_name_the_user_line():
+    src = "__device__ void mss_user_field(double t, const double* p, double* f) {\n" \
+          "  f[0] = undefined_thing;\n}\n"
+    with pytest.raises(native.MssError, match=r"user_field\.hip:2:.*undefined_thing") as e:
+        native.Sampler(src)
+    assert e.value.status == native.MSS_E_INVALID
+    with pytest.raises(native.MssError, match="mss_user_field"):
+        native.Sampler("int unrelated;")
+
+
+def test_sampler_integrate_validates_before_launch():
+    from tests import user_fields as F
+    s = native.Sampler(F.LZ_SOURCE)
+    L = native.lib()
+    prob = W.Problem(1, [W.Term(W.CONST, W.Z, a=1.0)], 0.0, 1e-6, 10, 2, 28, True)
+    pk = native.PackedProblem(prob)
+    dummy = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    assert L.mss_sampler_integrate(s._h, pk.ref, None, dummy, None, None, None) == native.MSS_E_INVALID
+    assert "no terms" in native.last_error()
+    pk = native.PackedProblem(prob.replace(terms=[], params=np.zeros(3)))
+    assert L.mss_sampler_integrate(s._h, pk.ref, None, dummy, None, None, None) == native.MSS_E_INVALID
+    assert "params" in native.last_error()
+    assert L.mss_sampler_integrate(None, pk.ref, None, dummy, None, None, None) == native.MSS_E_INVALID
+    s.close()
