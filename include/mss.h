@@ -278,6 +278,15 @@ typedef struct mss_batch_info_t {
 mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const int64_t* param_off,
                                  const mss_batch_options* options, mss_batch_plan** out);
 
+/* As mss_batch_plan_create, with every simulation's field from one user
+ * sampler (a parameter sweep of one compiled field function in a single
+ * persistent launch).  Every problem must have n_terms = 0.  The sampler
+ * must outlive the plan; it is loaded on the device current at each run. */
+mss_status mss_batch_plan_create_sampled(int32_t n, const mss_problem* problems,
+                                         const int64_t* param_off,
+                                         const mss_batch_options* options, mss_sampler sampler,
+                                         mss_batch_plan** out);
+
 /* Packed offsets (host arrays of n + 1 entries each; any may be NULL). */
 mss_status mss_batch_layout(const mss_batch_plan* plan, int64_t* psi0_off, int64_t* state_off,
                             int64_t* op_off);

@@ -13,6 +13,7 @@ total interval count rounded to a power of two).
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import math
 import os
@@ -30,14 +31,16 @@ def _arch() -> str:
     return f"{getattr(p, 'gcnArchName', p.name)}:{p.multi_processor_count}cu"
 
 
-def shape_key(problems) -> str:
+def shape_key(problems, sampler=None) -> str:
     spins = sorted({p.spin_twice for p in problems})
     taus = sorted({p.n_squares for p in problems if p.spin_twice == 2})
     fines = sorted({p.n_fine for p in problems})
     frames = sorted({bool(p.rotating_frame) for p in problems})
     total = sum(p.n_samples for p in problems)
     return json.dumps({"arch": _arch(), "spins": spins, "taus": taus, "fines": fines,
-                       "frames": frames, "intervals_log2": int(round(math.log2(max(total, 1))))},
+                       "frames": frames, "intervals_log2": int(round(math.log2(max(total, 1)))),
+                       "sampler": (hashlib.sha256(sampler.source.encode()).hexdigest()[:16]
+                                   if sampler is not None else None)},
                       sort_keys=True)
 
 
@@ -69,9 +72,12 @@ def _time(plan: "native.BatchPlan", bufs: dict, what: str, reps: int) -> float:
 
 
 def tune(problems, cache_path: Optional[str] = DEFAULT_CACHE, reps: int = 3,
-         target_fine_steps: float = 2e8, verbose: bool = False) -> Dict[str, int]:
-    """Options for BatchPlan(problems, **options), tuned (or read from the cache)."""
-    key = shape_key(problems)
+         target_fine_steps: float = 2e8, verbose: bool = False,
+         sampler: "Optional[native.Sampler]" = None) -> Dict[str, int]:
+    """Options for BatchPlan(problems, **options), tuned (or read from the cache).
+    With a sampler the trials run its integrator and the cache key includes
+    a hash of its source."""
+    key = shape_key(problems, sampler)
     cache = {}
     if cache_path and os.path.exists(cache_path):
         try:
@@ -90,7 +96,7 @@ def tune(problems, cache_path: Optional[str] = DEFAULT_CACHE, reps: int = 3,
     trials: List[dict] = []
 
     def run(opts: dict, what: str) -> float:
-        plan = native.BatchPlan(smp, **opts)
+        plan = native.BatchPlan(smp, sampler=sampler, **opts)
         bufs = plan.allocate(store_u=False)
         ms = _time(plan, bufs, what, reps)
         plan.close()
@@ -124,6 +130,6 @@ def tune(problems, cache_path: Optional[str] = DEFAULT_CACHE, reps: int = 3,
     return best
 
 
-def tuned_plan(problems, use_graph: bool = False, **kw) -> "native.BatchPlan":
-    opts = tune(problems, **kw)
-    return native.BatchPlan(problems, use_graph=use_graph, **opts)
+def tuned_plan(problems, use_graph: bool = False, sampler=None, **kw) -> "native.BatchPlan":
+    opts = tune(problems, sampler=sampler, **kw)
+    return native.BatchPlan(problems, use_graph=use_graph, sampler=sampler, **opts)

@@ -23,6 +23,7 @@ struct mss_batch_plan {
   int64_t op_total = 0;
   int grid_blocks = 0;
   mss_batch_options opt{};
+  mss_sampler sampler = nullptr;  // field source of every simulation, or null (field programs)
   // device descriptors
   void* desc = nullptr;
   size_t o_sims = 0, o_terms = 0;
@@ -104,22 +105,29 @@ mss_status bind(mss_batch_plan* P, const double* params, const double* psi0, dou
   return MSS_OK;
 }
 
+// The sampler's work integrator on the current device (null without one).
+mss_status user_function(mss_batch_plan* P, hipFunction_t* fn) {
+  *fn = nullptr;
+  return P->sampler ? api_sampler_work_function(P->sampler, fn) : MSS_OK;
+}
+
 mss_status enqueue(mss_batch_plan* P, bool integrate, bool scan, void* ws, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (integrate)
-    e = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks, st);
+  hipFunction_t fn = nullptr;
+  if (integrate) {
+    mss_status s = user_function(P, &fn);
+    if (s != MSS_OK) return s;
+    e = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks, st, fn);
+  }
   if (e == hipSuccess && scan) e = launch_work_scan(P->dev, st);
   if (e == hipSuccess) e = hipEventRecord(P->last_run, st);
   if (e != hipSuccess) return api_hip_fail(e, "batch launch");
   return MSS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const int64_t* param_off,
-                                 const mss_batch_options* options, mss_batch_plan** out) {
+mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* param_off,
+                       const mss_batch_options* options, mss_sampler sampler,
+                       mss_batch_plan** out) {
   if (!out) return api_fail(MSS_E_INVALID, "out is NULL");
   *out = nullptr;
   if (n < 1) return api_fail(MSS_E_INVALID, "a batch needs at least one simulation");
@@ -163,6 +171,7 @@ mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const i
   if (!P) return api_fail(MSS_E_NOMEM, "host allocation failed");
   P->n = n;
   P->opt = opt;
+  P->sampler = sampler;
   P->work.scan_e = scan_e;
   P->psi0_off.assign(n + 1, 0);
   P->state_off.assign(n + 1, 0);
@@ -202,6 +211,28 @@ mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const i
   P->grid_blocks = (int)std::max<int64_t>(1, std::min(blocks, (P->work.n_items + 3) / 4));
   *out = P;
   return api_ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+mss_status mss_batch_plan_create(int32_t n, const mss_problem* problems, const int64_t* param_off,
+                                 const mss_batch_options* options, mss_batch_plan** out) {
+  return create_plan(n, problems, param_off, options, nullptr, out);
+}
+
+mss_status mss_batch_plan_create_sampled(int32_t n, const mss_problem* problems,
+                                         const int64_t* param_off,
+                                         const mss_batch_options* options, mss_sampler sampler,
+                                         mss_batch_plan** out) {
+  if (out) *out = nullptr;
+  if (!sampler) return api_fail(MSS_E_INVALID, "sampler is NULL");
+  if (n >= 1 && problems)
+    for (int i = 0; i < n; ++i)
+      if (problems[i].n_terms != 0)
+        return api_fail(MSS_E_INVALID, "simulation %d: a sampler problem carries no terms", i);
+  return create_plan(n, problems, param_off, options, sampler, out);
 }
 
 mss_status mss_batch_layout(const mss_batch_plan* P, int64_t* psi0_off, int64_t* state_off,
@@ -252,13 +283,15 @@ mss_status mss_batch_run(mss_batch_plan* P, const double* params, const double* 
       (void)hipGraphExecDestroy(P->exec);
       P->exec = nullptr;
     }
+    hipFunction_t fn = nullptr;
+    if ((s = user_function(P, &fn)) != MSS_OK) return s;
     hipError_t e = hipSuccess;
     if (!P->capture_stream) e = hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking);
     hipGraph_t g = nullptr;
     if (e == hipSuccess) e = hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
       hipError_t el = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks,
-                                            P->capture_stream);
+                                            P->capture_stream, fn);
       if (el == hipSuccess) el = launch_work_scan(P->dev, P->capture_stream);
       hipError_t e2 = hipStreamEndCapture(P->capture_stream, &g);
       e = el != hipSuccess ? el : e2;

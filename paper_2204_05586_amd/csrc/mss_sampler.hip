@@ -20,6 +20,7 @@ struct mss_sampler_s {
   struct Module {
     hipModule_t mod = nullptr;
     hipFunction_t fn[2] = {nullptr, nullptr};  // spin-1/2, spin-1
+    hipFunction_t work = nullptr;              // batched work-queue integrator
   };
   std::vector<char> code;
   std::string log;
@@ -72,6 +73,7 @@ mss_status load_on_current(mss_sampler s, const mss_sampler_s::Module** out) {
     if (e != hipSuccess) return api_hip_fail(e, "loading the user sampler's code object");
     e = hipModuleGetFunction(&m.fn[0], m.mod, "mss_user_integrate_2");
     if (e == hipSuccess) e = hipModuleGetFunction(&m.fn[1], m.mod, "mss_user_integrate_3");
+    if (e == hipSuccess) e = hipModuleGetFunction(&m.work, m.mod, "mss_user_work_integrate");
     if (e != hipSuccess) {
       (void)hipModuleUnload(m.mod);
       return api_hip_fail(e, "user sampler kernels");
@@ -83,6 +85,16 @@ mss_status load_on_current(mss_sampler s, const mss_sampler_s::Module** out) {
 }
 
 }  // namespace
+
+namespace mss {
+mss_status api_sampler_work_function(mss_sampler s, hipFunction_t* fn) {
+  const mss_sampler_s::Module* m = nullptr;
+  mss_status st = load_on_current(s, &m);
+  if (st != MSS_OK) return st;
+  *fn = m->work;
+  return MSS_OK;
+}
+}  // namespace mss
 
 extern "C" {
 

@@ -12,6 +12,7 @@
 #pragma once
 
 #include "mss_device.h"
+#include "mss_work_device.h"
 
 __device__ void mss_user_field(double t, const double* params, double* field);
 
@@ -33,4 +34,17 @@ extern "C" __global__ void __launch_bounds__(256) mss_user_integrate_2(const mss
 
 extern "C" __global__ void __launch_bounds__(256) mss_user_integrate_3(const mss::IntervalGrid g) {
   mss::integrate_lanes<3>(MssUserField{}, g);
+}
+
+// Every descriptor of a batch takes its field from the user function.
+struct MssUserSource {
+  __device__ __forceinline__ MssUserField operator()(const mss::IntegrateWorkArgs&,
+                                                     const mss::SimDesc&) const {
+    return MssUserField{};
+  }
+};
+
+extern "C" __global__ void __launch_bounds__(256) mss_user_work_integrate(
+    const mss::IntegrateWorkArgs A) {
+  mss::work_integrate_loop(A, MssUserSource{});
 }

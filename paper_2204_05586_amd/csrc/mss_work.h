@@ -14,25 +14,9 @@
 #include <vector>
 
 #include "mss_internal.h"
+#include "mss_work_device.h"
 
 namespace mss {
-
-struct SimDesc {
-  double t_start, dt_out, dt;
-  int64_t k_first;   // first interval integrated by this descriptor
-  int64_t k_count;   // intervals integrated (0: none)
-  int64_t K_total;   // length of the whole sequence (for the scan)
-  int64_t item_off;  // first integrator work item
-  const double* params;
-  const double* psi0;  // [N]
-  double* psi;         // [K_total][N]
-  double* psi_final;   // [N] or null
-  double* U;           // [K_total][N][N]
-  double* scan_ws;     // scan levels 1..top: per level [n_l][N][N] then [n_l][N]
-  int32_t spin_twice, n_terms, term_off, n_fine;
-  int32_t tau, frame, slices_log2, top;  // top: scan levels above 0; -1: no scan
-  int32_t method, pad;
-};
 
 // Scan geometry of a sequence of K operators with tiles of `tile`
 // (= 64 E) operators: levels above 0 and the scratch (bytes) of levels 1..top.
@@ -81,9 +65,11 @@ DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_
                     const std::vector<size_t>& o_reduce, const std::vector<size_t>& o_apply);
 
 // Enqueue the integrator (counter cleared by a kernel first) over every
-// range of the work set; grid_blocks 256-thread workgroups.
+// range of the work set; grid_blocks 256-thread workgroups.  user_fn: the
+// work integrator of a user sampler's module (field from the sampler,
+// descriptors carry no terms), or null for the field-program kernel.
 hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, int grid_blocks,
-                                 hipStream_t st);
+                                 hipStream_t st, hipFunction_t user_fn = nullptr);
 // Enqueue the scan of every scanning sequence (reduce up, apply down).
 hipError_t launch_work_scan(const DevWork& w, hipStream_t st);
 

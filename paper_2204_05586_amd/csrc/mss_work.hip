@@ -51,20 +51,6 @@ __device__ __forceinline__ int find_segment(const int64_t* __restrict__ prefix, 
   return lo;
 }
 
-__device__ __forceinline__ int64_t wave_broadcast(int64_t v) {
-  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
-  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
-  return ((int64_t)hi << 32) | (uint32_t)lo;
-}
-
-struct IntegrateWorkArgs {
-  const SimDesc* sims;
-  const mss_term* terms;
-  unsigned long long* counter;
-  int64_t n_items;
-  int32_t n_sims;
-};
-
 struct ScanWorkArgs {
   const SimDesc* sims;
   const int64_t* tiles;  // prefix over sequences at this level
@@ -77,39 +63,16 @@ __global__ void work_reset_kernel(unsigned long long* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
 }
 
-template <int N>
-__device__ __forceinline__ void work_item(const IntegrateWorkArgs& A, const SimDesc& s,
-                                          int64_t local, int lane) {
-  const int sl = s.slices_log2;
-  const int64_t j = local * (64 >> sl) + (lane >> sl);  // interval within the range
-  const int slice = lane & ((1 << sl) - 1);
-  const bool active = j < s.k_count;
-  const int64_t k = s.k_first + j;
-  Mat<N> U;
-  double tk;
-  interval_operator<N>(TableTerms{A.terms + s.term_off, s.n_terms}, s.params, s.t_start, s.dt_out,
-                       s.dt, s.n_fine, s.tau, s.frame, s.method, k, slice, sl, active, U, &tk);
-  if (active && slice == 0) store_mat<N>(s.U + (size_t)k * 2 * N * N, U);
-}
+// Field-program source of a descriptor: its slice of the term table.
+struct TableSource {
+  __device__ __forceinline__ TableTerms operator()(const IntegrateWorkArgs& A,
+                                                   const SimDesc& s) const {
+    return TableTerms{A.terms + s.term_off, s.n_terms};
+  }
+};
 
 __global__ void __launch_bounds__(256) work_integrate_kernel(const IntegrateWorkArgs A) {
-  const int lane = threadIdx.x & 63;
-  for (;;) {
-    int64_t item = 0;
-    if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
-    item = wave_broadcast(item);
-    if (item >= A.n_items) break;
-    int lo = 0, hi = A.n_sims - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (A.sims[mid].item_off <= item) lo = mid;
-      else hi = mid - 1;
-    }
-    const SimDesc& s = A.sims[lo];
-    const int64_t local = item - s.item_off;
-    if (s.spin_twice == 2) work_item<3>(A, s, local, lane);
-    else work_item<2>(A, s, local, lane);
-  }
+  work_integrate_loop(A, TableSource{});
 }
 
 // Element count of a sequence at a scan level and the start of that level's
@@ -293,10 +256,17 @@ DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_
 }
 
 hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, int grid_blocks,
-                                 hipStream_t st) {
+                                 hipStream_t st, hipFunction_t user_fn) {
   if (w.n_items == 0) return hipSuccess;
   hipLaunchKernelGGL(work_reset_kernel, dim3(1), dim3(64), 0, st, counter);
   IntegrateWorkArgs a{w.sims, w.terms, counter, w.n_items, w.n_sims};
+  if (user_fn) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* args[] = {&a};
+    return hipModuleLaunchKernel(user_fn, (unsigned)grid_blocks, 1, 1, 256, 1, 1, 0, st, args,
+                                 nullptr);
+  }
   hipLaunchKernelGGL(work_integrate_kernel, dim3(grid_blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }

@@ -32,7 +32,7 @@ EXPORTS = [
     "mss_server_clock", "mss_server_destroy", "mss_adjoint_plan_create",
     "mss_adjoint_workspace_size", "mss_adjoint_param_count", "mss_adjoint_run",
     "mss_adjoint_plan_destroy", "mss_sampler_create", "mss_sampler_log", "mss_sampler_integrate",
-    "mss_sampler_solve", "mss_sampler_destroy",
+    "mss_sampler_solve", "mss_sampler_destroy", "mss_batch_plan_create_sampled",
 ]
 
 MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
@@ -128,6 +128,8 @@ def lib() -> C.CDLL:
         i64p = C.POINTER(C.c_int64)
         L.mss_batch_plan_create.argtypes = [C.c_int32, PP, i64p, C.POINTER(BatchOptions),
                                             C.POINTER(vp)]
+        L.mss_batch_plan_create_sampled.argtypes = [C.c_int32, PP, i64p,
+                                                    C.POINTER(BatchOptions), vp, C.POINTER(vp)]
         L.mss_batch_layout.argtypes = [vp, i64p, i64p, i64p]
         L.mss_batch_workspace_size.argtypes = [vp, C.c_int32, C.POINTER(sz)]
         L.mss_batch_info.argtypes = [vp, C.POINTER(BatchInfo)]
@@ -170,7 +172,8 @@ def lib() -> C.CDLL:
                      "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
                      "mss_adjoint_plan_create", "mss_adjoint_workspace_size",
                      "mss_adjoint_param_count", "mss_adjoint_run", "mss_sampler_create",
-                     "mss_sampler_integrate", "mss_sampler_solve"):
+                     "mss_sampler_integrate", "mss_sampler_solve",
+                     "mss_batch_plan_create_sampled"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -377,10 +380,12 @@ class BatchPlan:
 
     The packed layout puts simulation i's initial/final state at
     psi0_off[i], its states at state_off[i] and its operators at op_off[i]
-    (complex units).  Parameters are concatenated in simulation order."""
+    (complex units).  Parameters are concatenated in simulation order.
+    sampler: a ``Sampler`` giving every simulation's field (problems then
+    carry no terms); kept alive by the plan."""
 
     def __init__(self, problems, slices_spin_half=0, slices_spin_one=0, waves_per_simd=0,
-                 use_graph=False, scan_per_lane=0):
+                 use_graph=False, scan_per_lane=0, sampler: "Optional[Sampler]" = None):
         self.problems = list(problems)
         n = len(self.problems)
         self.packed = [PackedProblem(p) for p in self.problems]
@@ -400,9 +405,13 @@ class BatchPlan:
                         "waves_per_simd": int(waves_per_simd), "use_graph": bool(use_graph),
                         "scan_per_lane": int(scan_per_lane)}
         h = C.c_void_p()
-        check(lib().mss_batch_plan_create(
-            n, arr, self.param_off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(opt),
-            C.byref(h)))
+        offp = self.param_off.ctypes.data_as(C.POINTER(C.c_int64))
+        self.sampler = sampler
+        if sampler is None:
+            check(lib().mss_batch_plan_create(n, arr, offp, C.byref(opt), C.byref(h)))
+        else:
+            check(lib().mss_batch_plan_create_sampled(n, arr, offp, C.byref(opt), sampler._h,
+                                                      C.byref(h)))
         self.handle = h
         self.n = n
         offs = [np.zeros(n + 1, dtype=np.int64) for _ in range(3)]

@@ -188,3 +188,87 @@ def test_simulator_with_source(dev, oracle):
     assert np.max(np.abs(res.state.cpu().numpy() - ref["psi"])) <= TOL
     assert np.max(np.abs(res.time_evolution.cpu().numpy() - ref["U"])) <= TOL
     assert np.max(np.abs(res.spin.cpu().numpy() - oracle.spin_projection(ref["psi"]))) <= TOL
+
+
+def _sweep(seed=8):
+    """A sweep of the Landau-Zener field over (beta, delta, f_q) with uneven
+    lengths, both spins and both frame settings."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for K in (1, 63, 64, 65, 700, 2049, 9000):
+        for spin_twice in (1, 2):
+            beta = BETA * rng.uniform(0.5, 2.0)
+            delta = DELTA * rng.uniform(0.5, 2.0)
+            fq = rng.uniform(-300.0, 300.0) if spin_twice == 2 else 0.0
+            L = int(rng.integers(1, 13))
+            frame = bool(rng.integers(0, 2))
+            psi0 = W.random_state(spin_twice + 1, rng)
+            probs.append(W.Problem(spin_twice, [], -K * DT / 2, DT, K, L, int(rng.integers(12, 29)),
+                                   frame, params=np.array([beta, delta, fq]), psi0=psi0))
+    return probs
+
+
+def test_sampled_batch_matches_oracle_and_alone(dev, oracle, samplers):
+    """One persistent launch over a parameter sweep of one compiled field
+    function: every simulation vs the oracle, and vs the single-simulation
+    sampler path with the same lane-slice count."""
+    from paper_2204_05586_amd import native
+    probs = _sweep()
+    plan = native.BatchPlan(probs, slices_spin_half=1, slices_spin_one=1, sampler=samplers["lz"])
+    bufs = plan.allocate(store_u=True)
+    print(f"[gpu] sampled batch n={plan.n} info={plan.info()}", flush=True)
+    plan.run(bufs)
+    dev.cuda.synchronize()
+    worst_ref = worst_alone = 0.0
+    for i, p in enumerate(probs):
+        got = {k: v.cpu().numpy() for k, v in plan.split(bufs, i).items()}
+        ref = oracle.solve(p, want_U=True, field_fn=F.lz_field)
+        d = max(float(np.max(np.abs(got[k] - ref[k]))) for k in ("U", "psi", "psi_final"))
+        assert d <= TOL, (i, p.n_samples, d)
+        alone = _run(samplers["lz"], p, launch=(1, 256))
+        worst_alone = max(worst_alone, float(np.max(np.abs(got["U"] - alone["U"]))))
+        worst_ref = max(worst_ref, d)
+    print(f"sampled batch: vs oracle {worst_ref:.3e}, vs alone {worst_alone:.3e}", flush=True)
+    assert worst_alone <= 1e-13
+    plan.close()
+
+
+def test_sampled_batch_graph_replays(dev, samplers):
+    from paper_2204_05586_amd import native
+    probs = _sweep(seed=9)
+    eager = native.BatchPlan(probs, sampler=samplers["lz"])
+    e = eager.allocate(store_u=True)
+    eager.run(e)
+    graph = native.BatchPlan(probs, use_graph=True, sampler=samplers["lz"])
+    g = graph.allocate(store_u=True)
+    for rep in range(3):
+        print(f"[gpu] sampled batch graph replay {rep}", flush=True)
+        g["psi"].zero_()
+        graph.run(g)
+        dev.cuda.synchronize()
+        assert dev.equal(g["psi"], e["psi"]) and dev.equal(g["U"], e["U"])
+    eager.close()
+    graph.close()
+
+
+def test_sampled_batch_autotuned(dev, oracle, samplers, tmp_path):
+    from paper_2204_05586_amd import autotune
+    probs = _sweep(seed=10)
+    plan = autotune.tuned_plan(probs, sampler=samplers["lz"], cache_path=str(tmp_path / "t.json"),
+                               reps=1)
+    bufs = plan.allocate(store_u=False)
+    print(f"[gpu] autotuned sampled batch {plan.options}", flush=True)
+    plan.run(bufs)
+    dev.cuda.synchronize()
+    for i in (0, len(probs) // 2, len(probs) - 1):
+        got = plan.split(bufs, i)
+        ref = oracle.solve(probs[i], field_fn=F.lz_field)
+        assert np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"])) <= TOL
+    plan.close()
+
+
+def test_sampled_batch_rejects_terms(dev, samplers):
+    from paper_2204_05586_amd import native
+    probs = _sweep()[:2] + [W.spin_half_rabi(n_samples=10)]
+    with pytest.raises(native.MssError, match="no terms"):
+        native.BatchPlan(probs, sampler=samplers["lz"])
