@@ -231,6 +231,7 @@ void mss_server::run() {
       WorkSet ws;
       Inflight inf;
       inf.slot = slot;
+      double round_steps = 0;
       for (Request* r : work) {
         const double w = (r->N == 3 ? 1.0 : 1.0 / 16.0) * r->prob.n_fine;
         const int per = 64 >> api_ilog2(std::min(opt.slices, r->prob.n_fine));
@@ -249,7 +250,7 @@ void mss_server::run() {
         d.U = r->d_U;
         d.scan_ws = r->d_scan;
         r->next_k += k;
-        fine_steps += (double)k * r->prob.n_fine;
+        round_steps += (double)k * r->prob.n_fine;
         if (last) inf.finishing.push_back(r->ticket);
       }
       ws.finalize();
@@ -274,6 +275,7 @@ void mss_server::run() {
         ++round;
         std::lock_guard<std::mutex> lock(mu);
         ++rounds;
+        fine_steps += round_steps;
       }
     }
     if (e != hipSuccess) {
