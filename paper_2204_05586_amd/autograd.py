@@ -36,10 +36,10 @@ def _function():
 
     class FinalPopulation(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, params, plan, bufs, owner, stream):
+        def forward(ctx, params, plan, bufs, owner):
             if params is not None:
                 bufs["params"].copy_(params.detach())
-            plan.run(bufs, stream=stream)
+            plan.run(bufs)  # on the current stream, like the copies around it
             grad = bufs["grad"][:plan.n_grad].clone()
             ctx.save_for_backward(grad)
             ctx.owner = owner
@@ -49,8 +49,8 @@ def _function():
         def backward(ctx, grad_loss):
             (grad,) = ctx.saved_tensors
             if not ctx.needs_input_grad[0]:
-                return None, None, None, None, None
-            return grad * grad_loss[ctx.owner], None, None, None, None
+                return None, None, None, None
+            return grad * grad_loss[ctx.owner], None, None, None
 
     _FinalPopulation.fn = FinalPopulation
     return FinalPopulation
@@ -66,7 +66,9 @@ class PopulationModel:
     ``initial_params()`` returns it as a device tensor.
 
     ``model(params)`` returns the [n] losses with gradient flowing to
-    ``params`` (float64, on the device, length ``n_params``)."""
+    ``params`` (float64, on the device, length ``n_params``).  Everything
+    runs on torch's current stream.  Calls reuse the model's buffers, so one
+    model is not for concurrent use from several threads."""
 
     def __init__(self, problems, level_m: int, device: str = "cuda"):
         torch = _torch()
@@ -85,7 +87,7 @@ class PopulationModel:
         return p.clone() if p is not None else _torch().zeros(0, dtype=_torch().float64,
                                                               device=self.device)
 
-    def __call__(self, params, stream=None):
+    def __call__(self, params):
         torch = _torch()
         if self.n_params:
             if params is None or params.dtype != torch.float64 or params.numel() != self.n_params:
@@ -93,7 +95,7 @@ class PopulationModel:
             if params.device != self.bufs["params"].device:
                 raise ValueError("params must live on the plan's device")
         return _function().apply(params.contiguous() if self.n_params else None, self.plan,
-                                 self.bufs, self.owner, stream)
+                                 self.bufs, self.owner)
 
     def final_states(self):
         """Final states of the last call (packed as mss_batch_layout)."""
@@ -103,8 +105,9 @@ class PopulationModel:
         self.plan.close()
 
 
-def final_population(problems, level_m: int, params, stream=None,
+def final_population(problems, level_m: int, params,
                      model: Optional[PopulationModel] = None):
-    """One-shot form: losses of ``problems`` at ``params`` (differentiable)."""
+    """One-shot form: losses of ``problems`` at ``params`` (differentiable),
+    computed on the current stream."""
     m = model or PopulationModel(problems, level_m, device=str(params.device))
-    return m(params, stream=stream)
+    return m(params)
