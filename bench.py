@@ -43,8 +43,7 @@ MEASURED_TRAFFIC = {
 
 
 # sources that define the batched integrator (work_integrate_kernel)
-INTEGRATOR_SOURCES = ("mss_device.h", "mss_internal.h", "mss_work.h", "mss_work_device.h",
-                      "mss_work.hip")
+INTEGRATOR_SOURCES = ("mss_device.h", "mss_internal.h", "mss_work.h", "mss_work.hip")
 
 
 def kernel_source_hash() -> str:
@@ -121,34 +120,24 @@ def bench_plain(prob, steps: int, warmup: int) -> dict:
             "launch": {"slices": launch[0], "block": launch[1]}, "tau": prob.n_squares}
 
 
-def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool,
-                  scan: str = "auto") -> dict:
+def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool) -> dict:
     import torch
     from paper_2204_05586_amd import autotune, native
     t0 = time.perf_counter()
     opts = autotune.tune(problems, cache_path=None) if tune else {}
     tune_s = time.perf_counter() - t0
-    if scan != "auto":
-        opts = {**opts, "fused_scan": scan == "fused"}
-    fused = bool(opts.get("fused_scan", False))
     plan = native.BatchPlan(problems, **opts)
     bufs = plan.allocate(store_u=False)
     stream = torch.cuda.current_stream()
     fine = sum(p.fine_steps for p in problems)
 
     def step(ev=None):
-        # fused: one launch (states inside the integrator); else the
-        # integrator, then the separate scan, timed apart
         if ev:
             ev[0].record(stream)
-        if fused:
-            plan.run(bufs, stream=stream)
-        else:
-            plan.integrate(bufs, stream=stream)
+        plan.integrate(bufs, stream=stream)
         if ev:
             ev[1].record(stream)
-        if not fused:
-            plan.propagate(bufs, stream=stream)
+        plan.propagate(bufs, stream=stream)
         if ev:
             ev[2].record(stream)
 
@@ -167,7 +156,7 @@ def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool
     plan.close()
     out = {"value": fine * steps / wall, "ms_per_step": wall / steps * 1e3,
            "integrate_ms": statistics.mean(integ), "propagate_ms": statistics.mean(prop),
-           "fine_steps": fine, "info": info, "options": opts, "tune_s": tune_s, "fused": fused}
+           "fine_steps": fine, "info": info, "options": opts, "tune_s": tune_s}
     if graph_reps > 0:
         gplan = native.BatchPlan(problems, use_graph=True, **opts)
         gplan.run(bufs, stream=stream)  # capture + first replay
@@ -274,9 +263,6 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="planner defaults, no autotuning")
-    ap.add_argument("--scan", default="auto", choices=["auto", "fused", "separate"],
-                    help="batched states: fused into the integrator launch, separate scan, "
-                         "or the autotuner's choice (separate without tuning)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
                     help="target CPU seconds of the oracle sample (0: skip)")
     ap.add_argument("--serve-rates", default="10,100,1000",
@@ -302,25 +288,22 @@ def main():
     if args.workload == "batched_sensing":
         problems = W.batched_sensing(seed=2, n_sims=args.n_sims)
         tau = problems[0].n_squares
-        res = bench_batched(problems, args.steps, args.warmup, args.graph_reps, not args.no_tune,
-                            args.scan)
-        kernel = "batch_integrate_scan_kernel" if res["fused"] else "batch_integrate_kernel"
+        res = bench_batched(problems, args.steps, args.warmup, args.graph_reps, not args.no_tune)
+        kernel = "batch_integrate_kernel"
         plain = (bench_plain(W.spin_one_sensing(), args.plain_steps, 3)
                  if args.plain_steps > 0 else None)
         value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
             res["fine_steps"]
         config = {"workload": f"batched_sensing: {len(problems)} spin-1 simulations, seed 2, "
                               f"durations U(10,100) ms, dt_out 5e-7 s",
-                  "mode": ("batched (persistent integrator with the chained scan fused in, "
-                           "one launch)" if res["fused"] else
-                           "batched (persistent integrator + segmented scan, eager launches)"),
+                  "mode": "batched (persistent integrator + segmented scan, eager launches)",
                   "n_sims": len(problems), "total_intervals": res["info"]["total_samples"],
                   "n_fine": 10, "fine_steps": fine, "n_squares": tau, "rotating_frame": True,
                   "work_items": res["info"]["n_items"], "grid_blocks": res["info"]["grid_blocks"],
                   "scan_levels": res["info"]["scan_levels"], "autotuned": res["options"],
                   "autotune_s": round(res["tune_s"], 2)}
         extra = {"integrate_ms_mean": round(integ_ms, 3),
-                 "propagate_ms_mean": None if res["fused"] else round(res["propagate_ms"], 3),
+                 "propagate_ms_mean": round(res["propagate_ms"], 3),
                  "graph_ms_per_step": round(res.get("graph_ms_per_step", 0.0), 3) or None,
                  "plain": ({k: (round(v, 4) if isinstance(v, float) else v)
                             for k, v in plain.items()} if plain else None),
@@ -344,10 +327,6 @@ def main():
     roofline = None
     if args.workload != "spin_half_rabi":
         flops = spin_one_flops_per_fine_step(tau) * fine
-        if kernel == "batch_integrate_scan_kernel":
-            # plus the ordered product: one 3x3 complex matrix-vector product
-            # (9 complex multiply-adds) per interval
-            flops += 72 * res["info"]["total_samples"]
         achieved = flops / (integ_ms * 1e-3) / 1e12
         traffic = MEASURED_TRAFFIC.get((kernel, args.workload))
         roofline = {"bound": "alu", "achieved": round(achieved, 3),

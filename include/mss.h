@@ -261,13 +261,6 @@ typedef struct mss_batch_options {
   int32_t use_graph;        /* 1: capture the batch as one HIP graph, replayed while the
                                buffer pointers stay the same */
   int32_t scan_per_lane;    /* operators per lane in the scan tiles: 2, 4 or 8 (0: 4) */
-  int32_t fused_scan;       /* 1: mss_batch_run computes the states inside the integrator
-                               launch (a chained single-pass scan: each work item waits for
-                               the state leaving the item before it); the operators are then
-                               written only when U is given, and the workspace holds only
-                               per-item flags and states.  Such a plan runs through
-                               mss_batch_run only (mss_batch_integrate / _propagate give
-                               MSS_E_UNSUPPORTED).  0: separate scan. */
 } mss_batch_options;
 
 typedef struct mss_batch_info_t {
@@ -306,8 +299,7 @@ mss_status mss_batch_info(const mss_batch_plan* plan, mss_batch_info_t* info);
 
 /* Run the batch: operators (into U, or the workspace when U is NULL), then
  * states psi and (optional) psi_final, all device arrays in the packed
- * layout.  Asynchronous on `stream`.  With fused_scan, U may be NULL and
- * no operator is stored. */
+ * layout.  Asynchronous on `stream`. */
 mss_status mss_batch_run(mss_batch_plan* plan, const double* params, const double* psi0,
                          double* psi, double* psi_final, double* U, void* ws, size_t ws_bytes,
                          void* stream);

@@ -3,13 +3,10 @@
 Picks, for a batch of simulations, the launch options of ``BatchPlan``:
 lane-slices per interval for each spin class (how many lanes share one
 interval's fine steps), the persistent integrator's resident waves per SIMD
-(grid size), the scan tile (operators per lane, tile = 64 x that), and
-whether the states are computed inside the integrator launch (fused
-chained scan) or by the separate scan.  It times trial runs on a strided
-sample of the batch (coordinate descent: integrator options on
-integrator-only launches, the scan tile on scan-only launches, then whole
-runs fused vs separate, each the median of a few HIP-event-timed
-repetitions)
+(grid size), and the scan tile (operators per lane, tile = 64 x that).  It
+times trial runs on a strided sample of the batch (coordinate descent:
+integrator options on integrator-only launches, then the scan tile on
+scan-only launches, each the median of a few HIP-event-timed repetitions)
 and caches the winner on disk, keyed by GPU architecture and the batch's
 shape (spins, squaring counts, fine steps per interval, frame, and the
 total interval count rounded to a power of two).
@@ -58,7 +55,7 @@ def sample(problems, target_fine_steps: float = 2e8) -> list:
 def _time(plan: "native.BatchPlan", bufs: dict, what: str, reps: int) -> float:
     import torch
     stream = torch.cuda.current_stream()
-    call = {"integrate": plan.integrate, "propagate": plan.propagate, "run": plan.run}[what]
+    call = plan.integrate if what == "integrate" else plan.propagate
     if what == "propagate":
         plan.integrate(bufs, stream=stream)
     call(bufs, stream=stream)  # warm-up
@@ -123,11 +120,6 @@ def tune(problems, cache_path: Optional[str] = DEFAULT_CACHE, reps: int = 3,
         if ms < scan_ms:
             scan_best, scan_ms = e, ms
     best = {**best, "scan_per_lane": scan_best}
-    # states inside the integrator launch (chained scan) vs the separate scan
-    if run({**best, "fused_scan": True}, "run") < run({**best, "fused_scan": False}, "run"):
-        best = {**best, "fused_scan": True}
-    else:
-        best = {**best, "fused_scan": False}
     if cache_path:
         cache[key] = {"options": best, "trials": trials, "sample_sims": len(smp)}
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)

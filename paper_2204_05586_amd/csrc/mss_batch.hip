@@ -54,23 +54,13 @@ void release(mss_batch_plan* p) {
 }
 
 // Workspace: counter (256 B) | operators, when the caller keeps no U |
-// per-simulation scan scratch.  Fused plans: counter | item flags | the
-// state leaving each item (6 doubles).
+// per-simulation scan scratch.
 size_t scan_base(const mss_batch_plan* P, bool store_u) {
   return 256 + (store_u ? 0 : a256((size_t)P->op_total * 16));
 }
 
-size_t fused_tile_off(const mss_batch_plan* P) {
-  return 256 + a256((size_t)P->work.n_items * 8);
-}
-
-size_t workspace_bytes(const mss_batch_plan* P, bool store_u) {
-  if (P->opt.fused_scan) return fused_tile_off(P) + a256((size_t)P->work.n_items * 48);
-  return scan_base(P, store_u) + P->scan_bytes;
-}
-
 mss_status check_ws(const mss_batch_plan* P, bool store_u, const void* ws, size_t ws_bytes) {
-  const size_t need = workspace_bytes(P, store_u);
+  const size_t need = scan_base(P, store_u) + P->scan_bytes;
   if (!ws || ws_bytes < need)
     return api_fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", need,
                     ws ? ws_bytes : (size_t)0);
@@ -88,7 +78,7 @@ T* shift(T* base, int64_t off) {
 mss_status bind(mss_batch_plan* P, const double* params, const double* psi0, double* psi,
                 double* psi_final, double* U, void* ws) {
   char* base = (char*)ws;
-  double* ops = U ? U : (P->opt.fused_scan ? nullptr : (double*)(base + 256));
+  double* ops = U ? U : (double*)(base + 256);
   const void* key[6] = {params, psi0, psi, psi_final, ops, ws};
   bool same = P->have_upload;
   for (int i = 0; i < 6 && same; ++i) same = P->uploaded[i] == key[i];
@@ -104,8 +94,8 @@ mss_status bind(mss_batch_plan* P, const double* params, const double* psi0, dou
     d.psi0 = shift(psi0, 2 * P->psi0_off[i]);
     d.psi = shift(psi, 2 * P->state_off[i]);
     d.psi_final = shift(psi_final, 2 * P->psi0_off[i]);
-    d.U = ops ? ops + 2 * P->op_off[i] : nullptr;
-    d.scan_ws = P->opt.fused_scan ? nullptr : (double*)(base + sb + P->scan_off[i]);
+    d.U = ops + 2 * P->op_off[i];
+    d.scan_ws = (double*)(base + sb + P->scan_off[i]);
   }
   P->work.pack(P->image.data(), &P->o_sims, &P->o_terms, &P->o_reduce, &P->o_apply);
   hipError_t e = hipMemcpy(P->desc, P->image.data(), P->image.size(), hipMemcpyHostToDevice);
@@ -118,31 +108,12 @@ mss_status bind(mss_batch_plan* P, const double* params, const double* psi0, dou
 // The sampler's work integrator on the current device (null without one).
 mss_status user_function(mss_batch_plan* P, hipFunction_t* fn) {
   *fn = nullptr;
-  return P->sampler ? api_sampler_work_function(P->sampler, P->opt.fused_scan != 0, fn) : MSS_OK;
-}
-
-// Fused form: integrator with the ordered product, one launch (plus the
-// counter and flag clears).
-hipError_t launch_fused(mss_batch_plan* P, void* ws, bool store_u, hipStream_t st,
-                        hipFunction_t fn) {
-  char* base = (char*)ws;
-  return launch_work_integrate_scan(P->dev, (unsigned long long*)base,
-                                    (unsigned long long*)(base + 256),
-                                    (double*)(base + fused_tile_off(P)), store_u ? 1 : 0,
-                                    P->grid_blocks, st, fn);
+  return P->sampler ? api_sampler_work_function(P->sampler, fn) : MSS_OK;
 }
 
 mss_status enqueue(mss_batch_plan* P, bool integrate, bool scan, void* ws, hipStream_t st) {
   hipError_t e = hipSuccess;
   hipFunction_t fn = nullptr;
-  if (P->opt.fused_scan) {
-    mss_status s = user_function(P, &fn);
-    if (s != MSS_OK) return s;
-    e = launch_fused(P, ws, P->uploaded[4] != nullptr, st, fn);
-    if (e == hipSuccess) e = hipEventRecord(P->last_run, st);
-    if (e != hipSuccess) return api_hip_fail(e, "batch launch");
-    return MSS_OK;
-  }
   if (integrate) {
     mss_status s = user_function(P, &fn);
     if (s != MSS_OK) return s;
@@ -171,8 +142,6 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
   if (opt.scan_per_lane != 0 && opt.scan_per_lane != 2 && opt.scan_per_lane != 4 &&
       opt.scan_per_lane != 8)
     return api_fail(MSS_E_INVALID, "scan_per_lane must be 0, 2, 4 or 8");
-  if (opt.fused_scan != 0 && opt.fused_scan != 1)
-    return api_fail(MSS_E_INVALID, "fused_scan must be 0 or 1");
   const int scan_e = opt.scan_per_lane ? opt.scan_per_lane : kScanPerLane;
   for (int i = 0; i < n; ++i) {
     mss_status s = api_validate_problem(&problems[i]);
@@ -279,7 +248,7 @@ mss_status mss_batch_layout(const mss_batch_plan* P, int64_t* psi0_off, int64_t*
 
 mss_status mss_batch_workspace_size(const mss_batch_plan* P, int32_t store_u, size_t* bytes) {
   if (!P || !bytes) return api_fail(MSS_E_INVALID, "plan and bytes are required");
-  *bytes = workspace_bytes(P, store_u != 0);
+  *bytes = scan_base(P, store_u != 0) + P->scan_bytes;
   return api_ok();
 }
 
@@ -321,14 +290,9 @@ mss_status mss_batch_run(mss_batch_plan* P, const double* params, const double* 
     hipGraph_t g = nullptr;
     if (e == hipSuccess) e = hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-      hipError_t el;
-      if (P->opt.fused_scan) {
-        el = launch_fused(P, ws, U != nullptr, P->capture_stream, fn);
-      } else {
-        el = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks,
-                                   P->capture_stream, fn);
-        if (el == hipSuccess) el = launch_work_scan(P->dev, P->capture_stream);
-      }
+      hipError_t el = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks,
+                                            P->capture_stream, fn);
+      if (el == hipSuccess) el = launch_work_scan(P->dev, P->capture_stream);
       hipError_t e2 = hipStreamEndCapture(P->capture_stream, &g);
       e = el != hipSuccess ? el : e2;
     }
@@ -346,8 +310,6 @@ mss_status mss_batch_run(mss_batch_plan* P, const double* params, const double* 
 mss_status mss_batch_integrate(mss_batch_plan* P, const double* params, double* U, void* ws,
                                size_t ws_bytes, void* stream) {
   if (!P) return api_fail(MSS_E_INVALID, "plan is NULL");
-  if (P->opt.fused_scan)
-    return api_fail(MSS_E_UNSUPPORTED, "a fused-scan plan runs through mss_batch_run only");
   mss_status s = check_ws(P, U != nullptr, ws, ws_bytes);
   if (s != MSS_OK) return s;
   // the integrator reads no states: keep whatever state pointers are bound
@@ -363,8 +325,6 @@ mss_status mss_batch_propagate(mss_batch_plan* P, const double* psi0, double* ps
                                double* psi_final, const double* U, void* ws, size_t ws_bytes,
                                void* stream) {
   if (!P) return api_fail(MSS_E_INVALID, "plan is NULL");
-  if (P->opt.fused_scan)
-    return api_fail(MSS_E_UNSUPPORTED, "a fused-scan plan runs through mss_batch_run only");
   if (!psi0 || !psi) return api_fail(MSS_E_INVALID, "psi0 and psi are required");
   mss_status s = check_ws(P, U != nullptr, ws, ws_bytes);
   if (s != MSS_OK) return s;

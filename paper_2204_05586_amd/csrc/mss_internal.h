@@ -32,10 +32,9 @@ int api_ilog2(int x);
 // launch shape (lane-slices per interval, block size) of one simulation
 mss_status api_resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block);
 
-// work-queue integrator (plain or fused with the ordered product) of a user
-// sampler's module on the current device
+// work-queue integrator of a user sampler's module on the current device
 // (loads the module there on first use)
-mss_status api_sampler_work_function(mss_sampler s, bool fused, hipFunction_t* fn);
+mss_status api_sampler_work_function(mss_sampler s, hipFunction_t* fn);
 
 hipError_t launch_integrate(int N, const IntegrateArgs& a, int block, hipStream_t st);
 hipError_t launch_scan_reduce(int N, const double* M, int64_t n, double* agg, hipStream_t st);

@@ -21,7 +21,6 @@ struct mss_sampler_s {
     hipModule_t mod = nullptr;
     hipFunction_t fn[2] = {nullptr, nullptr};  // spin-1/2, spin-1
     hipFunction_t work = nullptr;              // batched work-queue integrator
-    hipFunction_t work_scan = nullptr;         // its fused form (with the ordered product)
   };
   std::vector<char> code;
   std::string log;
@@ -75,8 +74,6 @@ mss_status load_on_current(mss_sampler s, const mss_sampler_s::Module** out) {
     e = hipModuleGetFunction(&m.fn[0], m.mod, "mss_user_integrate_2");
     if (e == hipSuccess) e = hipModuleGetFunction(&m.fn[1], m.mod, "mss_user_integrate_3");
     if (e == hipSuccess) e = hipModuleGetFunction(&m.work, m.mod, "mss_user_work_integrate");
-    if (e == hipSuccess)
-      e = hipModuleGetFunction(&m.work_scan, m.mod, "mss_user_work_integrate_scan");
     if (e != hipSuccess) {
       (void)hipModuleUnload(m.mod);
       return api_hip_fail(e, "user sampler kernels");
@@ -90,11 +87,11 @@ mss_status load_on_current(mss_sampler s, const mss_sampler_s::Module** out) {
 }  // namespace
 
 namespace mss {
-mss_status api_sampler_work_function(mss_sampler s, bool fused, hipFunction_t* fn) {
+mss_status api_sampler_work_function(mss_sampler s, hipFunction_t* fn) {
   const mss_sampler_s::Module* m = nullptr;
   mss_status st = load_on_current(s, &m);
   if (st != MSS_OK) return st;
-  *fn = fused ? m->work_scan : m->work;
+  *fn = m->work;
   return MSS_OK;
 }
 }  // namespace mss

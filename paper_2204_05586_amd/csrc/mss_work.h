@@ -70,14 +70,6 @@ DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_
 // descriptors carry no terms), or null for the field-program kernel.
 hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, int grid_blocks,
                                  hipStream_t st, hipFunction_t user_fn = nullptr);
-// Fused form: the integrator and the ordered product in one launch (every
-// sequence integrated whole and scanned); flags [n_items] are cleared by a
-// kernel first, tile_out holds [n_items][6] doubles.  store_u: also write
-// the operators.  user_fn: the fused kernel of a user sampler's module.
-hipError_t launch_work_integrate_scan(const DevWork& w, unsigned long long* counter,
-                                      unsigned long long* flags, double* tile_out, int store_u,
-                                      int grid_blocks, hipStream_t st,
-                                      hipFunction_t user_fn = nullptr);
 // Enqueue the scan of every scanning sequence (reduce up, apply down).
 hipError_t launch_work_scan(const DevWork& w, hipStream_t st);
 

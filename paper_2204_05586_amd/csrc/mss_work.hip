@@ -75,18 +75,6 @@ __global__ void __launch_bounds__(256) work_integrate_kernel(const IntegrateWork
   work_integrate_loop(A, TableSource{});
 }
 
-__global__ void __launch_bounds__(256) work_integrate_scan_kernel(const IntegrateWorkArgs A) {
-  work_integrate_loop<true>(A, TableSource{});
-}
-
-// Clears the fused form's item flags (a kernel, so graph captures hold no
-// memset nodes).
-__global__ void __launch_bounds__(256) work_clear_flags_kernel(unsigned long long* flags,
-                                                               int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flags[i] = 0ull;
-}
-
 // Element count of a sequence at a scan level and the start of that level's
 // arrays in the sequence's scratch (levels >= 1).
 template <int N, int E>
@@ -271,7 +259,7 @@ hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, 
                                  hipStream_t st, hipFunction_t user_fn) {
   if (w.n_items == 0) return hipSuccess;
   hipLaunchKernelGGL(work_reset_kernel, dim3(1), dim3(64), 0, st, counter);
-  IntegrateWorkArgs a{w.sims, w.terms, counter, w.n_items, w.n_sims, 0, nullptr, nullptr};
+  IntegrateWorkArgs a{w.sims, w.terms, counter, w.n_items, w.n_sims};
   if (user_fn) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -280,25 +268,6 @@ hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, 
                                  nullptr);
   }
   hipLaunchKernelGGL(work_integrate_kernel, dim3(grid_blocks), dim3(256), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_work_integrate_scan(const DevWork& w, unsigned long long* counter,
-                                      unsigned long long* flags, double* tile_out, int store_u,
-                                      int grid_blocks, hipStream_t st, hipFunction_t user_fn) {
-  if (w.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(work_reset_kernel, dim3(1), dim3(64), 0, st, counter);
-  hipLaunchKernelGGL(work_clear_flags_kernel, dim3((unsigned)((w.n_items + 255) / 256)), dim3(256),
-                     0, st, flags, w.n_items);
-  IntegrateWorkArgs a{w.sims, w.terms, counter, w.n_items, w.n_sims, store_u, flags, tile_out};
-  if (user_fn) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    void* args[] = {&a};
-    return hipModuleLaunchKernel(user_fn, (unsigned)grid_blocks, 1, 1, 256, 1, 1, 0, st, args,
-                                 nullptr);
-  }
-  hipLaunchKernelGGL(work_integrate_scan_kernel, dim3(grid_blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -72,7 +72,7 @@ class Launch(C.Structure):
 class BatchOptions(C.Structure):
     _fields_ = [("slices_spin_half", C.c_int32), ("slices_spin_one", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("use_graph", C.c_int32),
-                ("scan_per_lane", C.c_int32), ("fused_scan", C.c_int32)]
+                ("scan_per_lane", C.c_int32)]
 
 
 class ServerOptions(C.Structure):
@@ -382,12 +382,10 @@ class BatchPlan:
     psi0_off[i], its states at state_off[i] and its operators at op_off[i]
     (complex units).  Parameters are concatenated in simulation order.
     sampler: a ``Sampler`` giving every simulation's field (problems then
-    carry no terms); kept alive by the plan.  fused_scan: states computed
-    inside the integrator launch (``run`` only; no operator buffer needed)."""
+    carry no terms); kept alive by the plan."""
 
     def __init__(self, problems, slices_spin_half=0, slices_spin_one=0, waves_per_simd=0,
-                 use_graph=False, scan_per_lane=0, sampler: "Optional[Sampler]" = None,
-                 fused_scan=False):
+                 use_graph=False, scan_per_lane=0, sampler: "Optional[Sampler]" = None):
         self.problems = list(problems)
         n = len(self.problems)
         self.packed = [PackedProblem(p) for p in self.problems]
@@ -401,11 +399,11 @@ class BatchPlan:
             self.param_off[:n] = np.concatenate([[0], np.cumsum(counts)[:-1]])
         self.n_params_total = int(counts.sum())
         opt = BatchOptions(int(slices_spin_half), int(slices_spin_one), int(waves_per_simd),
-                           int(bool(use_graph)), int(scan_per_lane), int(bool(fused_scan)))
+                           int(bool(use_graph)), int(scan_per_lane))
         self.options = {"slices_spin_half": int(slices_spin_half),
                         "slices_spin_one": int(slices_spin_one),
                         "waves_per_simd": int(waves_per_simd), "use_graph": bool(use_graph),
-                        "scan_per_lane": int(scan_per_lane), "fused_scan": bool(fused_scan)}
+                        "scan_per_lane": int(scan_per_lane)}
         h = C.c_void_p()
         offp = self.param_off.ctypes.data_as(C.POINTER(C.c_int64))
         self.sampler = sampler

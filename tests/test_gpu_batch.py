@@ -152,77 +152,3 @@ def test_autotuned_plan_matches_oracle(torch_dev, oracle, tmp_path):
         got = plan.split(bufs, i)
         assert np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"])) <= TOL
     plan.close()
-
-
-# ---- fused form: integrator and chained single-pass scan in one launch -----
-
-@pytest.mark.parametrize("store_u", [True, False])
-def test_fused_scan_matches_oracle(torch_dev, oracle, store_u):
-    """Mixed spins, uneven K (1 ... 70,000), random L, frames and methods
-    of sampling, states computed inside the integrator launch: every
-    simulation vs the oracle, and vs the separate-scan plan."""
-    from paper_2204_05586_amd import native
-    probs = _mixed_batch(seed=31)
-    fused = native.BatchPlan(probs, fused_scan=True)
-    bf = _run(fused, store_u=store_u)
-    plain = native.BatchPlan(probs)
-    bp = _run(plain, store_u=True)
-    worst = worst_plain = 0.0
-    for i, p in enumerate(probs):
-        ref = oracle.solve(p, want_U=store_u)
-        got = {k: v.cpu().numpy() for k, v in fused.split(bf, i).items()}
-        keys = ("psi", "psi_final") + (("U",) if store_u else ())
-        d = max(float(np.max(np.abs(got[k] - ref[k]))) for k in keys)
-        assert d <= TOL, (i, p.name, p.n_samples, d)
-        other = plain.split(bp, i)
-        dp = max(float(np.max(np.abs(got[k] - other[k].cpu().numpy()))) for k in keys)
-        worst, worst_plain = max(worst, d), max(worst_plain, dp)
-    print(f"fused (store_u={store_u}): vs oracle {worst:.3e}, vs separate scan {worst_plain:.3e}",
-          flush=True)
-    assert worst_plain <= 1e-12
-    fused.close()
-    plain.close()
-
-
-@pytest.mark.parametrize("S", [1, 2, 4, 8])
-def test_fused_scan_slices(torch_dev, oracle, S):
-    """Items of 64 / S intervals: the chain crosses item boundaries inside
-    each simulation for every lane-slice count."""
-    from paper_2204_05586_amd import native
-    probs = W.batched_sensing(seed=7, n_sims=6, dur_lo=0.0005, dur_hi=0.002)
-    probs += [W.random_problem(np.random.default_rng(S), 1, 3001, 8)]
-    plan = native.BatchPlan(probs, slices_spin_one=S, slices_spin_half=S, fused_scan=True)
-    bufs = _run(plan, store_u=False)
-    for i in range(len(probs)):
-        ref = oracle.solve(probs[i])
-        got = plan.split(bufs, i)
-        d = max(float(np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"]))),
-                float(np.max(np.abs(got["psi_final"].cpu().numpy() - ref["psi_final"]))))
-        assert d <= TOL, (S, i, d)
-    plan.close()
-
-
-def test_fused_scan_graph_replays_and_limits(torch_dev):
-    """Graph replays of the fused plan (flags cleared by a kernel each time)
-    reproduce the eager run; the separate halves are refused."""
-    import torch
-    from paper_2204_05586_amd import native
-    probs = _mixed_batch(seed=12)[:14]
-    eager = native.BatchPlan(probs, fused_scan=True)
-    be = _run(eager, store_u=False)
-    graph = native.BatchPlan(probs, use_graph=True, fused_scan=True)
-    bufs = graph.allocate(store_u=False)
-    for rep in range(3):
-        bufs["psi"].fill_(float("nan"))
-        print(f"[gpu] fused graph replay {rep}", flush=True)
-        graph.run(bufs)
-        torch.cuda.synchronize()
-        torch.randn(1000, device="cuda").sum()
-        assert torch.equal(bufs["psi"], be["psi"]) and torch.equal(bufs["psi_final"],
-                                                                   be["psi_final"])
-    with pytest.raises(native.MssError, match="mss_batch_run only"):
-        eager.integrate(be)
-    with pytest.raises(native.MssError, match="mss_batch_run only"):
-        eager.propagate(be)
-    eager.close()
-    graph.close()

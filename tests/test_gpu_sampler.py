@@ -272,19 +272,3 @@ def test_sampled_batch_rejects_terms(dev, samplers):
     probs = _sweep()[:2] + [W.spin_half_rabi(n_samples=10)]
     with pytest.raises(native.MssError, match="no terms"):
         native.BatchPlan(probs, sampler=samplers["lz"])
-
-
-def test_sampled_batch_fused_scan(dev, oracle, samplers):
-    from paper_2204_05586_amd import native
-    probs = _sweep(seed=13)
-    plan = native.BatchPlan(probs, sampler=samplers["lz"], fused_scan=True)
-    bufs = plan.allocate(store_u=True)
-    print(f"[gpu] sampled fused batch n={plan.n}", flush=True)
-    plan.run(bufs)
-    dev.cuda.synchronize()
-    for i, p in enumerate(probs):
-        got = {k: v.cpu().numpy() for k, v in plan.split(bufs, i).items()}
-        ref = oracle.solve(p, want_U=True, field_fn=F.lz_field)
-        d = max(float(np.max(np.abs(got[k] - ref[k]))) for k in ("U", "psi", "psi_final"))
-        assert d <= TOL, (i, p.n_samples, d)
-    plan.close()
