@@ -43,7 +43,8 @@ MEASURED_TRAFFIC = {
 
 
 # sources that define the batched integrator (work_integrate_kernel)
-INTEGRATOR_SOURCES = ("mss_device.h", "mss_internal.h", "mss_work.h", "mss_work.hip")
+INTEGRATOR_SOURCES = ("mss_device.h", "mss_internal.h", "mss_work.h", "mss_work_device.h",
+                      "mss_work.hip")
 
 
 def kernel_source_hash() -> str:
