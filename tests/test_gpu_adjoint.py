@@ -90,7 +90,7 @@ def test_autograd_function_matches_oracle(torch_dev, oracle):
     from paper_2204_05586_amd.autograd import PopulationModel
     probs = [_control_problem(2, frame=True, seed=11, extra=("cos",)),
              _control_problem(1, frame=True, seed=12, extra=("pwc",)),
-             _control_problem(2, frame=False, seed=13)]
+             _control_problem(2, frame=False, seed=13, extra=("cos", "sin"))]
     m = 1
     model = PopulationModel(probs, m)
     w = torch.tensor([0.7, -1.3, 2.0], dtype=torch.float64, device="cuda")
@@ -122,7 +122,7 @@ def test_autograd_gradcheck_small(torch_dev):
     short spin-1 control problem."""
     torch = torch_dev
     from paper_2204_05586_amd.autograd import PopulationModel
-    p = _control_problem(2, frame=True, seed=21, K=40, L=5)
+    p = _control_problem(2, frame=True, seed=21, K=40, L=5, extra=("cos", "pwc"))
     model = PopulationModel([p], 1)
     params = model.initial_params().requires_grad_(True)
     print("[gpu] gradcheck", flush=True)
@@ -137,7 +137,7 @@ def test_autograd_descent_lowers_loss(torch_dev):
     gradient would not)."""
     torch = torch_dev
     from paper_2204_05586_amd.autograd import PopulationModel
-    p = _control_problem(2, frame=True, seed=31)
+    p = _control_problem(2, frame=True, seed=31, extra=("cos",))
     model = PopulationModel([p], 1)
     x = model.initial_params().requires_grad_(True)
     losses = []
