@@ -378,7 +378,9 @@ __device__ __forceinline__ void adjoint_interval(const AdjArgs& A, const AdjDesc
   const double wgt[2][2] = {{kWPlus, kWMinus}, {kWMinus, kWPlus}};  // [node][exponential]
   for (int l = s.n_fine - 1; l >= 0; --l) {
     double th[2][4];
-    cf4_angles(terms, s.params, tk, l, s.dt, wr, th[0], th[1]);
+    NodeRotations rot;
+    if (wr != 0.0) rot.at(wr, l, s.dt);
+    cf4_angles(terms, s.params, tk, l, s.dt, wr, rot, th[0], th[1]);
     double gx[2], gy[2];
     for (int e = 1; e >= 0; --e) {
       Mat<N> E, dE;

@@ -238,7 +238,7 @@ __device__ __forceinline__ void lie_trotter_residual(const double th[4], int tau
   const double ninv = ldexp(1.0, -tau);
   const double z = th[2] * ninv;
   const double q = th[3] * ninv;
-  const double rho = hypot(th[0], th[1]);
+  const double rho = sqrt(fma(th[0], th[0], th[1] * th[1]));  // angles are far from overflow
   const double Phi = rho * ninv;
   double epr = 1.0, epi = 0.0;  // e^{i phi} = (theta_x + i theta_y) / rho
   if (rho > 0.0) {
@@ -273,14 +273,14 @@ __device__ __forceinline__ void lie_trotter_residual(const double th[4], int tau
   a.i[0][2] = -S2 * fma(e3i, e2r, -e3r * e2i);
   a.r[2][0] = -S2 * fma(e3r, e2r, -e3i * e2i);
   a.i[2][0] = -S2 * fma(e3i, e2r, e3r * e2i);
-  // diagonals, b1 = -z - q/3, b2 = 2q/3, b3 = z - q/3
-  const double q3 = q * (1.0 / 3.0);
-  const double b[3] = {-z - q3, 2.0 * q3, z - q3};
+  // diagonals, b1 = -z - q/3, b2 = 2q/3, b3 = z - q/3: the half-angle
+  // exponentials e^{i b_j / 2} are conj(h), conj(e^{-iq/3}) and conj(g)
+  const double shv[3] = {-hi, -e3i, -gi};  // sin(b_j / 2)
+  const double chv[3] = {hr, e3r, gr};     // cos(b_j / 2)
   const double k[3] = {S2, 2.0 * S2, S2};
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    double sh, ch;
-    sincos_small(0.5 * b[j], &sh, &ch);
+    const double sh = shv[j], ch = chv[j];
     const double mr = -2.0 * sh * sh;  // Re(e^{ib} - 1)
     const double mi = 2.0 * sh * ch;   // Im = sin b
     a.r[j][j] = fma(-k[j], 1.0 + mr, mr);
@@ -376,12 +376,50 @@ __device__ __forceinline__ void field_eval(const Terms& fp, const double* __rest
   f[0] = fx; f[1] = fy; f[2] = fz; f[3] = fq;
 }
 
+// Frame rotations of the two CF4 nodes of a run of fine steps: cos and sin
+// of wr tau_i at tau_i = (l + c_i) dt, taken directly at the run's first
+// step and advanced by the rotation over one fine step (angle addition),
+// so a step costs two complex products instead of two sines and cosines.
+struct NodeRotations {
+  double c[2], s[2];  // cos, sin of wr tau_i for the current step
+  double cd, sd;      // cos, sin of wr dt
+  __device__ __forceinline__ void start(double wr, int l, double dt) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double tau_i = ((double)l + (i == 0 ? kNode1 : kNode2)) * dt;
+      sincos_cw(wr * tau_i, &s[i], &c[i]);
+    }
+    sincos_cw(wr * dt, &sd, &cd);
+  }
+  // the node rotations of step l alone, taken directly (no step rotation)
+  __device__ __forceinline__ void at(double wr, int l, double dt) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double tau_i = ((double)l + (i == 0 ? kNode1 : kNode2)) * dt;
+      sincos_cw(wr * tau_i, &s[i], &c[i]);
+    }
+  }
+  __device__ __forceinline__ void advance() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double cn = fma(c[i], cd, -s[i] * sd);
+      const double sn = fma(s[i], cd, c[i] * sd);
+      c[i] = cn;
+      s[i] = sn;
+    }
+  }
+};
+
 // Angles theta_{1,2} = omega_bar_{1,2} dt of one CF4 fine step starting at
-// t_k + l dt, in the frame rotating at wr about z (wr = 0: lab frame).
+// t_k + l dt, in the frame rotating at wr about z (wr = 0: lab frame; then
+// rot is not read).
 template <class Terms>
 __device__ __forceinline__ void cf4_angles(const Terms& fp, const double* __restrict__ params,
                                            double tk, int l, double dt, double wr,
-                                           double th1[4], double th2[4]) {
+                                           const NodeRotations& rot, double th1[4],
+                                           double th2[4]) {
 #pragma clang fp contract(off)
   double w[2][4];
 #pragma unroll
@@ -393,8 +431,7 @@ __device__ __forceinline__ void cf4_angles(const Terms& fp, const double* __rest
     for (int j = 0; j < 4; ++j) w[i][j] = kTwoPi * f[j];
     if (wr != 0.0) {
       // (w_x + i w_y) e^{-i wr tau_i}
-      double s, c;
-      sincos_cw(wr * tau_i, &s, &c);
+      const double c = rot.c[i], s = rot.s[i];
       const double xr = w[i][0] * c + w[i][1] * s;
       const double xi = w[i][1] * c - w[i][0] * s;
       w[i][0] = xr;
@@ -493,9 +530,12 @@ __device__ __forceinline__ void interval_operator(const Terms& terms, const doub
     const int l0 = (int)(((int64_t)s * L) >> sl);
     const int l1 = (int)(((int64_t)(s + 1) * L) >> sl);
     if (method == 0) {
+      NodeRotations rot;
+      if (wr != 0.0) rot.start(wr, l0, dt);
       for (int l = l0; l < l1; ++l) {
         double th1[4], th2[4];
-        cf4_angles(terms, params, tk, l, dt, wr, th1, th2);
+        cf4_angles(terms, params, tk, l, dt, wr, rot, th1, th2);
+        if (wr != 0.0) rot.advance();
         Mat<N> E;
         Exponentiator<N>::apply(th1, tau, E);
         premultiply<N>(E, U);
