@@ -29,7 +29,10 @@
  * calls are DEVICE pointers (HIP device memory of the current device);
  * mss_problem and its term array are HOST memory and are only read during
  * the call.  `stream` is a hipStream_t (NULL: the default stream); work is
- * enqueued asynchronously and the library keeps no pointer after return.
+ * enqueued asynchronously.  The single-simulation calls keep no pointer
+ * after return; batch plans, adjoint plans and servers keep the device
+ * pointers of their last run or of admitted requests, as documented with
+ * each.
  *
  * Errors: every call returns an mss_status.  Arguments are validated on
  * the host before anything is launched; on failure nothing is launched and
