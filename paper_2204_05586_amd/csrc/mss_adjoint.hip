@@ -29,95 +29,102 @@
 namespace mss {
 
 // ---------------------------------------------------------------------------
-// one-direction dual numbers for the exponentiator set-up
+// two-direction dual numbers for the exponentiator set-up: v + x e_x + y e_y
+// with e_x, e_y nilpotent; x and y carry d / d theta_x and d / d theta_y
 // ---------------------------------------------------------------------------
-struct D1 {
-  double v, d;
+struct D2 {
+  double v, x, y;
 };
-__device__ __forceinline__ D1 operator+(D1 a, D1 b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ D1 operator-(D1 a, D1 b) { return {a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ D1 operator-(D1 a) { return {-a.v, -a.d}; }
-__device__ __forceinline__ D1 operator*(D1 a, D1 b) { return {a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
-__device__ __forceinline__ D1 operator*(double a, D1 b) { return {a * b.v, a * b.d}; }
-__device__ __forceinline__ D1 operator+(D1 a, double b) { return {a.v + b, a.d}; }
-__device__ __forceinline__ void sincos_d(D1 x, D1* s, D1* c) {
+__device__ __forceinline__ D2 operator+(D2 a, D2 b) { return {a.v + b.v, a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ D2 operator-(D2 a, D2 b) { return {a.v - b.v, a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ D2 operator-(D2 a) { return {-a.v, -a.x, -a.y}; }
+__device__ __forceinline__ D2 operator*(D2 a, D2 b) {
+  return {a.v * b.v, fma(a.x, b.v, a.v * b.x), fma(a.y, b.v, a.v * b.y)};
+}
+__device__ __forceinline__ D2 operator*(double a, D2 b) { return {a * b.v, a * b.x, a * b.y}; }
+__device__ __forceinline__ D2 operator+(D2 a, double b) { return {a.v + b, a.x, a.y}; }
+__device__ __forceinline__ void sincos_d2(D2 t, D2* s, D2* c) {
   double sv, cv;
-  sincos_small(x.v, &sv, &cv);
-  *s = {sv, cv * x.d};
-  *c = {cv, -sv * x.d};
+  sincos_small(t.v, &sv, &cv);
+  *s = {sv, cv * t.x, cv * t.y};
+  *c = {cv, -sv * t.x, -sv * t.y};
 }
 
-struct CD {
-  D1 r, i;
+struct CD2 {
+  D2 r, i;
 };
-__device__ __forceinline__ CD cmul(CD a, CD b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
-__device__ __forceinline__ CD conj(CD a) { return {a.r, -a.i}; }
+__device__ __forceinline__ CD2 cmul(CD2 a, CD2 b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+__device__ __forceinline__ CD2 conj(CD2 a) { return {a.r, -a.i}; }
 
-// Residual a = T - I and its derivative along theta_dir (same entries as
-// lie_trotter_residual, in dual arithmetic).
-__device__ __forceinline__ void lie_trotter_residual_tangent(const double th[4], int dir, int tau,
-                                                             Mat<3>& a, Mat<3>& da) {
+// Residual a = T - I and its derivatives along theta_x (dax) and theta_y
+// (day): the entries of lie_trotter_residual in dual arithmetic.  The
+// derivative of e^{i phi} is taken as 0 at rho = 0.
+__device__ __forceinline__ void lie_trotter_residual_tangent(const double th[4], int tau, Mat<3>& a,
+                                                             Mat<3>& dax, Mat<3>& day) {
   const double ninv = ldexp(1.0, -tau);
-  D1 t[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) t[j] = {th[j], j == dir ? 1.0 : 0.0};
-  const D1 z = ninv * t[2];
-  const D1 q = ninv * t[3];
-  const double rv = hypot(th[0], th[1]);
-  D1 rho = {rv, 0.0};
-  CD ep = {{1.0, 0.0}, {0.0, 0.0}};  // e^{i phi}
+  const D2 tx = {th[0], 1.0, 0.0}, ty = {th[1], 0.0, 1.0};
+  const D2 z = {th[2] * ninv, 0.0, 0.0};
+  const D2 q = {th[3] * ninv, 0.0, 0.0};
+  const double rv = sqrt(fma(th[0], th[0], th[1] * th[1]));
+  D2 rho = {rv, 0.0, 0.0};
+  CD2 ep = {{1.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};  // e^{i phi}
   if (rv > 0.0) {
     const double inv = 1.0 / rv;
-    rho.d = (th[0] * t[0].d + th[1] * t[1].d) * inv;
-    const D1 rinv = {inv, -rho.d * inv * inv};
-    ep = {t[0] * rinv, t[1] * rinv};
+    rho.x = th[0] * inv;
+    rho.y = th[1] * inv;
+    const D2 rinv = {inv, -rho.x * inv * inv, -rho.y * inv * inv};
+    ep = {tx * rinv, ty * rinv};
   }
-  const D1 Phi = ninv * rho;
-  D1 S, C;
-  sincos_d(0.5 * Phi, &S, &C);
-  const D1 S2 = S * S;
-  const D1 rs = kRsqrt2 * (2.0 * (S * C));
-  D1 sz, cz, sq, cq;
-  sincos_d(0.5 * z, &sz, &cz);
-  sincos_d((1.0 / 6.0) * q, &sq, &cq);
-  const CD eq = {cq, sq}, ez = {cz, sz};
-  const CD g = cmul(eq, conj(ez)), h = cmul(eq, ez);
-  const CD em = conj(ep);
-  const CD gm = cmul(g, em), gp = cmul(g, ep), hm = cmul(h, em), hp = cmul(h, ep);
+  const D2 Phi = ninv * rho;
+  D2 S, C;
+  sincos_d2(0.5 * Phi, &S, &C);
+  const D2 S2 = S * S;
+  const D2 rs = kRsqrt2 * (2.0 * (S * C));
+  D2 sz, cz, sq, cq;
+  sincos_d2(0.5 * z, &sz, &cz);
+  sincos_d2((1.0 / 6.0) * q, &sq, &cq);
+  const CD2 eq = {cq, sq}, ez = {cz, sz};
+  const CD2 g = cmul(eq, conj(ez)), h = cmul(eq, ez);
+  const CD2 em = conj(ep);
+  const CD2 gm = cmul(g, em), gp = cmul(g, ep), hm = cmul(h, em), hp = cmul(h, ep);
   // (-i rs) (x + i y) = rs y - i rs x
-  const CD off[4] = {gm, gp, hm, hp};
+  const CD2 off[4] = {gm, gp, hm, hp};
   const int oi[4] = {0, 1, 1, 2}, oj[4] = {1, 0, 2, 1};
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
-    const D1 re = rs * off[n].i, im = -(rs * off[n].r);
+    const D2 re = rs * off[n].i, im = -(rs * off[n].r);
     a.r[oi[n]][oj[n]] = re.v;
     a.i[oi[n]][oj[n]] = im.v;
-    da.r[oi[n]][oj[n]] = re.d;
-    da.i[oi[n]][oj[n]] = im.d;
+    dax.r[oi[n]][oj[n]] = re.x;
+    dax.i[oi[n]][oj[n]] = im.x;
+    day.r[oi[n]][oj[n]] = re.y;
+    day.i[oi[n]][oj[n]] = im.y;
   }
-  const CD e3 = conj(cmul(eq, eq));  // e^{-iq/3}
-  const CD e2 = cmul(ep, ep);        // e^{2i phi}
-  const CD t13 = cmul(e3, conj(e2)), t31 = cmul(e3, e2);
-  const D1 mS2 = -S2;
-  a.r[0][2] = (mS2 * t13.r).v;  da.r[0][2] = (mS2 * t13.r).d;
-  a.i[0][2] = (mS2 * t13.i).v;  da.i[0][2] = (mS2 * t13.i).d;
-  a.r[2][0] = (mS2 * t31.r).v;  da.r[2][0] = (mS2 * t31.r).d;
-  a.i[2][0] = (mS2 * t31.i).v;  da.i[2][0] = (mS2 * t31.i).d;
-  const D1 q3 = (1.0 / 3.0) * q;
-  const D1 b[3] = {-z - q3, 2.0 * q3, z - q3};
-  const D1 k[3] = {S2, 2.0 * S2, S2};
+  const CD2 e3 = conj(cmul(eq, eq));  // e^{-iq/3}
+  const CD2 e2 = cmul(ep, ep);        // e^{2i phi}
+  const CD2 t13 = cmul(e3, conj(e2)), t31 = cmul(e3, e2);
+  const D2 mS2 = -S2;
+  const D2 c02r = mS2 * t13.r, c02i = mS2 * t13.i, c20r = mS2 * t31.r, c20i = mS2 * t31.i;
+  a.r[0][2] = c02r.v;  dax.r[0][2] = c02r.x;  day.r[0][2] = c02r.y;
+  a.i[0][2] = c02i.v;  dax.i[0][2] = c02i.x;  day.i[0][2] = c02i.y;
+  a.r[2][0] = c20r.v;  dax.r[2][0] = c20r.x;  day.r[2][0] = c20r.y;
+  a.i[2][0] = c20i.v;  dax.i[2][0] = c20i.x;  day.i[2][0] = c20i.y;
+  // diagonals: half-angle exponentials e^{i b_j / 2} = conj(h), conj(e3), conj(g)
+  // for b = (-z - q/3, 2q/3, z - q/3)
+  const D2 shv[3] = {-h.i, -e3.i, -g.i};
+  const D2 chv[3] = {h.r, e3.r, g.r};
+  const D2 k[3] = {S2, 2.0 * S2, S2};
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    D1 sh, ch;
-    sincos_d(0.5 * b[j], &sh, &ch);
-    const D1 mr = -2.0 * (sh * sh);
-    const D1 mi = 2.0 * (sh * ch);
-    const D1 re = mr - k[j] * (mr + 1.0);
-    const D1 im = mi - k[j] * mi;
-    a.r[j][j] = re.v;
-    a.i[j][j] = im.v;
-    da.r[j][j] = re.d;
-    da.i[j][j] = im.d;
+    const D2 sh = shv[j], ch = chv[j];
+    const D2 mr = -2.0 * (sh * sh);
+    const D2 mi = 2.0 * (sh * ch);
+    const D2 re = mr - k[j] * (mr + 1.0);
+    const D2 im = mi - k[j] * mi;
+    a.r[j][j] = re.v;  dax.r[j][j] = re.x;  day.r[j][j] = re.y;
+    a.i[j][j] = im.v;  dax.i[j][j] = im.x;  day.i[j][j] = im.y;
   }
 }
 
@@ -141,42 +148,69 @@ __device__ __forceinline__ void matmul_add(const Mat<N>& A, const Mat<N>& B, Mat
     }
 }
 
-// (a, da) <- ((a + 2I) a, da a + (a + 2I) da)
-__device__ __forceinline__ void tangent_square(const Mat<3>& a, const Mat<3>& da, Mat<3>& a2,
-                                               Mat<3>& da2) {
+// One tangent residual squaring of (a, dx, dy) with b = a + 2I:
+//   dx' = dx a + b dx  -> f,   dy' = dy a + b dy  -> dx,   a' = b a  -> dy,
+// each written only after the matrix it overwrites is no longer read.  The
+// new state (a', dx', dy') is (dy, f, dx) and a is free: four register sets
+// rotate, so no matrix is copied.
+__device__ __forceinline__ void tangent_step(const Mat<3>& a, Mat<3>& dx, Mat<3>& dy, Mat<3>& f) {
   Mat<3> b = a;
   b.r[0][0] += 2.0;
   b.r[1][1] += 2.0;
   b.r[2][2] += 2.0;
-  matmul<3>(da, a, da2);
-  matmul_add<3>(b, da, da2);
-  matmul<3>(b, a, a2);
+  matmul<3>(dx, a, f);
+  matmul_add<3>(b, dx, f);
+  matmul<3>(dy, a, dx);
+  matmul_add<3>(b, dy, dx);
+  matmul<3>(b, a, dy);
 }
 
-// E = exp of the step angles (Lie-Trotter, tau residual squarings) and dE/dtheta_dir.
-__device__ __forceinline__ void exp_one_tangent(const double th[4], int dir, int tau, Mat<3>& E,
-                                                Mat<3>& dE) {
-  Mat<3> a, da;
-  lie_trotter_residual_tangent(th, dir, tau, a, da);
-  for (int s = 0; s + 2 <= tau; s += 2) {
-    tangent_square(a, da, E, dE);
-    tangent_square(E, dE, a, da);
+// E = exp of the step angles (Lie-Trotter, tau residual squarings) with
+// dE/dtheta_x and dE/dtheta_y: the derivatives of exactly the computed E.
+__device__ __forceinline__ void exp_one_tangent(const double th[4], int tau, Mat<3>& E,
+                                                Mat<3>& dEx, Mat<3>& dEy) {
+  Mat<3> A, X, Y, F;
+  lie_trotter_residual_tangent(th, tau, A, X, Y);
+  int s = 0;
+  for (; s + 4 <= tau; s += 4) {  // four steps bring the roles back to (A, X, Y)
+    tangent_step(A, X, Y, F);     // state (Y, F, X)
+    tangent_step(Y, F, X, A);     // state (X, A, F)
+    tangent_step(X, A, F, Y);     // state (F, Y, A)
+    tangent_step(F, Y, A, X);     // state (A, X, Y)
   }
-  if (tau & 1) {
-    tangent_square(a, da, E, dE);
-    a = E;
-    da = dE;
+  const int r = tau - s;
+  if (r == 0) {
+    E = A;
+    dEx = X;
+    dEy = Y;
+  } else if (r == 1) {
+    tangent_step(A, X, Y, F);
+    E = Y;
+    dEx = F;
+    dEy = X;
+  } else if (r == 2) {
+    tangent_step(A, X, Y, F);
+    tangent_step(Y, F, X, A);
+    E = X;
+    dEx = A;
+    dEy = F;
+  } else {
+    tangent_step(A, X, Y, F);
+    tangent_step(Y, F, X, A);
+    tangent_step(X, A, F, Y);
+    E = F;
+    dEx = Y;
+    dEy = A;
   }
-  E = a;
-  dE = da;
   E.r[0][0] += 1.0;
   E.r[1][1] += 1.0;
   E.r[2][2] += 1.0;
 }
 
-// Spin-1/2: E = cos(|theta|/2) I - i (sin(|theta|/2)/|theta|) theta.sigma and dE/dtheta_dir.
-__device__ __forceinline__ void exp_half_tangent(const double th[4], int dir, int /*tau*/,
-                                                 Mat<2>& E, Mat<2>& dE) {
+// Spin-1/2: E = cos(|theta|/2) I - i (sin(|theta|/2)/|theta|) theta.sigma and
+// dE/dtheta_dir for dir = x, y.
+__device__ __forceinline__ void exp_half_tangent(const double th[4], int /*tau*/, Mat<2>& E,
+                                                 Mat<2>& dEx, Mat<2>& dEy) {
   exp_half(th, 0, E);
   const double t2 = fma(th[0], th[0], fma(th[1], th[1], th[2] * th[2]));
   const double big = sqrt(t2);
@@ -197,29 +231,33 @@ __device__ __forceinline__ void exp_half_tangent(const double th[4], int dir, in
     dS_over = (0.5 * c - S) / t2;
   }
   const double dc_over = -0.5 * S;
-  const double td = th[dir];
-  const double dc = dc_over * td;
-  const double dS = dS_over * td;
-  const double ex = dir == 0 ? 1.0 : 0.0, ey = dir == 1 ? 1.0 : 0.0, ez = dir == 2 ? 1.0 : 0.0;
-  // d(S theta_j) = dS theta_j + S e_j
-  const double dx = fma(dS, th[0], S * ex), dy = fma(dS, th[1], S * ey), dz = fma(dS, th[2], S * ez);
-  dE.r[0][0] = dc;   dE.i[0][0] = -dz;
-  dE.r[0][1] = -dy;  dE.i[0][1] = -dx;
-  dE.r[1][0] = dy;   dE.i[1][0] = -dx;
-  dE.r[1][1] = dc;   dE.i[1][1] = dz;
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    Mat<2>& dE = dir == 0 ? dEx : dEy;
+    const double td = th[dir];
+    const double dc = dc_over * td;
+    const double dS = dS_over * td;
+    const double ex = dir == 0 ? 1.0 : 0.0, ey = dir == 1 ? 1.0 : 0.0;
+    // d(S theta_j) = dS theta_j + S e_j
+    const double dx = fma(dS, th[0], S * ex), dy = fma(dS, th[1], S * ey), dz = dS * th[2];
+    dE.r[0][0] = dc;   dE.i[0][0] = -dz;
+    dE.r[0][1] = -dy;  dE.i[0][1] = -dx;
+    dE.r[1][0] = dy;   dE.i[1][0] = -dx;
+    dE.r[1][1] = dc;   dE.i[1][1] = dz;
+  }
 }
 
 template <int N> struct TangentExp;
 template <> struct TangentExp<2> {
-  static __device__ __forceinline__ void apply(const double th[4], int dir, int tau, Mat<2>& E,
-                                               Mat<2>& dE) {
-    exp_half_tangent(th, dir, tau, E, dE);
+  static __device__ __forceinline__ void apply(const double th[4], int tau, Mat<2>& E,
+                                               Mat<2>& dEx, Mat<2>& dEy) {
+    exp_half_tangent(th, tau, E, dEx, dEy);
   }
 };
 template <> struct TangentExp<3> {
-  static __device__ __forceinline__ void apply(const double th[4], int dir, int tau, Mat<3>& E,
-                                               Mat<3>& dE) {
-    exp_one_tangent(th, dir, tau, E, dE);
+  static __device__ __forceinline__ void apply(const double th[4], int tau, Mat<3>& E,
+                                               Mat<3>& dEx, Mat<3>& dEy) {
+    exp_one_tangent(th, tau, E, dEx, dEy);
   }
 };
 
@@ -383,16 +421,14 @@ __device__ __forceinline__ void adjoint_interval(const AdjArgs& A, const AdjDesc
     cf4_angles(terms, s.params, tk, l, s.dt, wr, rot, th[0], th[1]);
     double gx[2], gy[2];
     for (int e = 1; e >= 0; --e) {
-      Mat<N> E, dE;
-      // x direction: E, dE/dtheta_x; then the state before E and the new costate
-      TangentExp<N>::apply(th[e], 0, s.tau, E, dE);
+      Mat<N> E, dEx, dEy;
+      // E with dE/dtheta_x and dE/dtheta_y; the state before E and the new costate
+      TangentExp<N>::apply(th[e], s.tau, E, dEx, dEy);
       double br[N], bi[N], nlr[N], nli[N];
       mat_h_vec<N>(E, pr, pi, br, bi);
-      gx[e] = bilinear<N>(lr, li, dE, br, bi);
+      gx[e] = bilinear<N>(lr, li, dEx, br, bi);
+      gy[e] = bilinear<N>(lr, li, dEy, br, bi);
       mat_h_vec<N>(E, lr, li, nlr, nli);
-      // y direction: dE/dtheta_y against the same costate and state
-      TangentExp<N>::apply(th[e], 1, s.tau, E, dE);
-      gy[e] = bilinear<N>(lr, li, dE, br, bi);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         pr[a] = br[a];
