@@ -173,10 +173,14 @@ def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool
     return out
 
 
-def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib: float) -> dict:
+def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib: float,
+                  burst: int = 0) -> dict:
     """Poisson request streams (70 % spin-1, 30 % spin-1/2, K log-uniform in
     [1e3, 1e6], 10 CF4 steps per interval) submitted at their arrival times
-    to one server; latency = completion - scheduled arrival."""
+    to one server; latency = completion - scheduled arrival.  With burst > 0,
+    also `burst` requests of the same mix submitted at once: the server's
+    capacity (fine steps/s from the first submission to the last
+    completion), with latency = completion - submission."""
     import queue
     import threading
     import numpy as np
@@ -219,6 +223,24 @@ def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib:
                                "mean_ms": round(float(lat.mean()), 3),
                                "submit_lag_p99_ms": round(float(np.percentile(lag, 99)), 3),
                                "fine_steps_per_s": round(steps / span, 1)}
+    if burst > 0:
+        reqs = W.serving_stream(1000.0, n_requests=burst, rate_index=len(all_rates) + 1)
+        t0 = srv.clock()
+        tickets = [(srv.submit(r.problem), r.problem.fine_steps) for r in reqs]
+        spin_one_steps = sum(r.problem.fine_steps for r in reqs if r.problem.spin_twice == 2)
+        lat, steps, last = [], 0, t0
+        for t, st_ in tickets:
+            info = srv.wait(t, 600.0)
+            lat.append(info["t_done"] - info["t_submit"])
+            last = max(last, info["t_done"])
+            steps += st_
+            srv.release(t)
+        lat = np.array(lat) * 1e3
+        out["burst"] = {"requests": burst, "fine_steps": steps, "spin_one_fine_steps": spin_one_steps,
+                        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                        "span_s": round(last - t0, 4),
+                        "fine_steps_per_s": round(steps / (last - t0), 1)}
     st = srv.stats()
     out["server"] = {"rounds": st["rounds"], "bytes_peak": st["bytes_peak"],
                      "budget": st["budget"]}
@@ -268,6 +290,8 @@ def main():
                     help="target CPU seconds of the oracle sample (0: skip)")
     ap.add_argument("--serve-rates", default="10,100,1000",
                     help="request rates (req/s) of the serving sweep, '' to skip")
+    ap.add_argument("--serve-burst", type=int, default=300,
+                    help="requests submitted at once to measure the server's capacity (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="target stream length per rate (requests = rate x seconds, <= 2000)")
     ap.add_argument("--adjoint-instances", type=int, default=1024,
@@ -353,7 +377,8 @@ def main():
     serving = None
     if args.serve_rates:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
-        serving = bench_serving(rates, args.serve_seconds, 2000, budget_gib=64.0)
+        serving = bench_serving(rates, args.serve_seconds, 2000, budget_gib=64.0,
+                                burst=args.serve_burst)
 
     base = (cpu_baseline(base_problems, args.cpu_baseline_seconds)
             if args.cpu_baseline_seconds > 0 else None)
