@@ -197,8 +197,10 @@ mss_status api_validate_problem(const mss_problem* p) { return validate_problem(
 
 namespace {
 
-mss_status resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block) {
+mss_status resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block,
+                          bool* given) {
   int S = in ? in->slices : 0;
+  if (given) *given = S != 0;
   int B = in ? in->block : 0;
   if (S == 0) S = plan_slices(p->n_samples, p->n_fine, device_cu_count());
   if (B == 0) B = 256;
@@ -217,8 +219,43 @@ mss_status resolve_launch(const mss_problem* p, const mss_launch* in, int* slice
 }  // namespace
 
 namespace mss {
-mss_status api_resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block) {
-  return resolve_launch(p, in, slices, block);
+mss_status api_resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block,
+                              bool* given) {
+  return resolve_launch(p, in, slices, block, given);
+}
+
+void api_plan_lane_segments(IntervalGrid& g, int S0, bool given, int64_t slots) {
+  const int64_t K = g.K;
+  const int L = g.L;
+  g.n_seg = 1;
+  g.seg_sl[0] = g.seg_sl[1] = ilog2(S0);
+  g.seg_k0[0] = 0;
+  g.seg_w0[0] = 0;
+  g.seg_k0[1] = K;
+  g.seg_w0[1] = 0;
+  if (given || slots <= 0) return;
+  const int64_t per0 = 64 / S0;
+  const int64_t W0 = (K + per0 - 1) / per0;
+  if (W0 <= slots) return;  // at most one round: the slice count already fills it
+  const int64_t full = (W0 / slots) * slots;
+  const int64_t k_main = full * per0;
+  const int64_t rest = K - k_main;
+  if (rest <= 0) return;
+  // the leftover intervals, sliced as finely as one round of waves allows
+  int S1 = S0;
+  const int cap = L < 64 ? L : 64;
+  while (S1 * 2 <= cap && (rest * S1 * 2 + 63) / 64 <= slots) S1 *= 2;
+  if ((L + S1 - 1) / S1 >= (L + S0 - 1) / S0) return;  // no shorter final round
+  g.n_seg = 2;
+  g.seg_sl[1] = ilog2(S1);
+  g.seg_k0[1] = k_main;
+  g.seg_w0[1] = full;
+}
+
+int64_t api_grid_waves(const IntervalGrid& g) {
+  const int j = g.n_seg - 1;
+  const int64_t per = 64 >> g.seg_sl[j];
+  return g.seg_w0[j] + (g.K - g.seg_k0[j] + per - 1) / per;
 }
 }  // namespace mss
 
@@ -251,7 +288,7 @@ mss_status mss_plan_launch(const mss_problem* p, mss_launch* out) {
   if (s != MSS_OK) return s;
   if (!out) return api_fail(MSS_E_INVALID, "out is NULL");
   int S, B;
-  if ((s = resolve_launch(p, nullptr, &S, &B)) != MSS_OK) return s;
+  if ((s = resolve_launch(p, nullptr, &S, &B, nullptr)) != MSS_OK) return s;
   out->slices = S;
   out->block = B;
   return api_ok();
@@ -283,7 +320,8 @@ mss_status mss_integrate(const mss_problem* p, const double* params, double* U, 
   if (!U) return api_fail(MSS_E_INVALID, "U is NULL");
   if (p->n_params > 0 && !params) return api_fail(MSS_E_INVALID, "params is NULL but n_params > 0");
   int S, B;
-  if ((s = resolve_launch(p, launch, &S, &B)) != MSS_OK) return s;
+  bool given = false;
+  if ((s = resolve_launch(p, launch, &S, &B, &given)) != MSS_OK) return s;
   IntegrateArgs a;
   memset(&a, 0, sizeof a);
   a.fp.n_terms = p->n_terms;
@@ -299,7 +337,7 @@ mss_status mss_integrate(const mss_problem* p, const double* params, double* U, 
   a.g.tau = p->spin_twice == 2 ? p->n_squares : 0;
   a.g.frame = p->rotating_frame;
   a.g.method = p->method;
-  a.g.slices_log2 = ilog2(S);
+  api_plan_lane_segments(a.g, S, given, integrate_slots(p->spin_twice + 1, B));
   hipError_t e = launch_integrate(p->spin_twice + 1, a, B, (hipStream_t)stream);
   if (e != hipSuccess) return api_hip_fail(e, "integrate launch");
   return api_ok();

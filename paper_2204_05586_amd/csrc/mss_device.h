@@ -561,7 +561,12 @@ __device__ __forceinline__ void interval_operator(const Terms& terms, const doub
 }
 
 // Time grid, outputs and options of one simulation's integrator launch
-// (everything but the field source).
+// (everything but the field source).  The intervals form up to two
+// segments with their own lane-slice counts: segment j holds intervals
+// [seg_k0[j], next segment's first or K) on waves from seg_w0[j] on, 64 /
+// 2^seg_sl[j] intervals per wave.  A second segment re-slices the intervals
+// left over after the last full round of waves more finely, so the final
+// round is short.
 struct IntervalGrid {
   const double* params;  // the simulation's parameter vector (may be null)
   double* U;             // [K][N][N] complex
@@ -573,22 +578,28 @@ struct IntervalGrid {
   int32_t L;
   int32_t tau;
   int32_t frame;
-  int32_t slices_log2;
   int32_t method;
+  int32_t n_seg;         // 1 or 2
+  int32_t seg_sl[2];     // log2 of the lane-slices per interval
   int32_t pad;
+  int64_t seg_k0[2];     // first interval of each segment
+  int64_t seg_w0[2];     // first wave of each segment
 };
 
 // Lane body of the single-simulation integrator: one lane per (interval k,
-// slice s), the S = 2^slices_log2 slices of an interval in consecutive
-// lanes of one wave; the whole wave must call it.  `terms` is any field
-// source field_eval accepts.
+// slice s), the S = 2^sl slices of an interval in consecutive lanes of one
+// wave; the whole wave must call it.  `terms` is any field source
+// field_eval accepts.
 template <int N, class Terms>
 __device__ __forceinline__ void integrate_lanes(const Terms& terms, const IntervalGrid& g) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int sl = g.slices_log2;
-  const int64_t k = gid >> sl;
-  const int s = (int)(gid & ((1 << sl) - 1));
-  const bool active = k < g.K;
+  const int64_t wave = gid >> 6;
+  const int lane = (int)(gid & 63);
+  const int j = (g.n_seg > 1 && wave >= g.seg_w0[1]) ? 1 : 0;  // uniform across the wave
+  const int sl = g.seg_sl[j];
+  const int64_t k = g.seg_k0[j] + ((wave - g.seg_w0[j]) << (6 - sl)) + (lane >> sl);
+  const int s = lane & ((1 << sl) - 1);
+  const bool active = k < (j + 1 < g.n_seg ? g.seg_k0[j + 1] : g.K);
   Mat<N> U;
   double tk;
   interval_operator<N>(terms, g.params, g.t_start, g.dt_out, g.dt, g.L, g.tau, g.frame, g.method,

@@ -29,8 +29,18 @@ mss_status api_validate_problem(const mss_problem* p);
 int api_device_cu_count();
 int api_plan_slices(int64_t K, int32_t L, int cu);
 int api_ilog2(int x);
-// launch shape (lane-slices per interval, block size) of one simulation
-mss_status api_resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block);
+// launch shape (lane-slices per interval, block size) of one simulation;
+// given: whether the caller fixed the slices
+mss_status api_resolve_launch(const mss_problem* p, const mss_launch* in, int* slices, int* block,
+                              bool* given);
+// lane segments of a grid launch with S0 slices (IntervalGrid), given the
+// number of waves that run at once (slots; 0: unknown, one segment)
+void api_plan_lane_segments(IntervalGrid& g, int S0, bool given, int64_t slots);
+// waves of a planned grid launch
+int64_t api_grid_waves(const IntervalGrid& g);
+// waves of integrate_kernel<N> in blocks of `block` threads that run at once
+// on the current device (0 if unknown)
+int64_t integrate_slots(int N, int block);
 
 // work-queue integrator of a user sampler's module on the current device
 // (loads the module there on first use)

@@ -72,9 +72,22 @@ __global__ void __launch_bounds__(256) spin_projection_kernel(const double* __re
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+int64_t integrate_slots(int N, int block) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  int blocks = 0;
+  const hipError_t e =
+      N == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, integrate_kernel<2>, block, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, integrate_kernel<3>, block, 0);
+  if (e != hipSuccess) return 0;
+  return (int64_t)blocks * (block / 64) * cu;
+}
+
 hipError_t launch_integrate(int N, const IntegrateArgs& a, int block, hipStream_t st) {
-  const int64_t lanes = a.g.K << a.g.slices_log2;
-  const int64_t grid = (lanes + block - 1) / block;
+  const int64_t grid = (api_grid_waves(a.g) * 64 + block - 1) / block;
   if (N == 2)
     hipLaunchKernelGGL(integrate_kernel<2>, dim3((unsigned)grid), dim3(block), 0, st, a);
   else

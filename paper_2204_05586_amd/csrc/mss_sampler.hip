@@ -167,7 +167,8 @@ mss_status mss_sampler_integrate(mss_sampler s, const mss_problem* p, const doub
   if (!U) return api_fail(MSS_E_INVALID, "U is NULL");
   if (p->n_params > 0 && !params) return api_fail(MSS_E_INVALID, "params is NULL but n_params > 0");
   int S, B;
-  if ((st = api_resolve_launch(p, launch, &S, &B)) != MSS_OK) return st;
+  bool given = false;
+  if ((st = api_resolve_launch(p, launch, &S, &B, &given)) != MSS_OK) return st;
   const mss_sampler_s::Module* m = nullptr;
   if ((st = load_on_current(s, &m)) != MSS_OK) return st;
   IntervalGrid g;
@@ -183,11 +184,15 @@ mss_status mss_sampler_integrate(mss_sampler s, const mss_problem* p, const doub
   g.tau = p->spin_twice == 2 ? p->n_squares : 0;
   g.frame = p->rotating_frame;
   g.method = p->method;
-  g.slices_log2 = api_ilog2(S);
-  const int64_t lanes = p->n_samples << g.slices_log2;
-  const unsigned grid = (unsigned)((lanes + B - 1) / B);
+  hipFunction_t fn = m->fn[p->spin_twice - 1];
+  int blocks = 0, cu = api_device_cu_count();
+  int64_t slots = 0;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, B, 0) == hipSuccess)
+    slots = (int64_t)blocks * (B / 64) * cu;
+  api_plan_lane_segments(g, S, given, slots);
+  const unsigned grid = (unsigned)((api_grid_waves(g) * 64 + B - 1) / B);
   void* args[] = {&g};
-  hipError_t e = hipModuleLaunchKernel(m->fn[p->spin_twice - 1], grid, 1, 1, (unsigned)B, 1, 1, 0,
+  hipError_t e = hipModuleLaunchKernel(fn, grid, 1, 1, (unsigned)B, 1, 1, 0,
                                        (hipStream_t)stream, args, nullptr);
   if (e != hipSuccess) return api_hip_fail(e, "user sampler integrate launch");
   return api_ok();
