@@ -35,9 +35,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # sources are unchanged.
 MEASURED_TRAFFIC = {
     ("batch_integrate_kernel", "batched_sensing"): {
-        "src": "94f74e6bda1595d1",
-        "fetch_kib": 3612.4375, "write_kib": 64048080.1875,
-        "bytes": int(round((3612.4375 * 2.000 + 64048080.1875 * 1.000) * 1024)),
+        "src": "d5e46f3bca4ba99c",
+        "fetch_kib": 3559.375, "write_kib": 64048457.5625,
+        "bytes": int(round((3559.375 * 2.000 + 64048457.5625 * 1.000) * 1024)),
     },
 }
 
