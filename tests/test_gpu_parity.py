@@ -81,11 +81,12 @@ def test_random_problems(dev, oracle, spin_twice, frame, K):
     _compare(_gpu(prob), oracle.solve(prob, want_U=True), name=f"random K={K}")
 
 
-def test_multilevel_scan(dev, oracle):
-    """K = 65537 needs three scan levels (256^2 < K)."""
+@pytest.mark.parametrize("K", [65537, 300001])
+def test_multilevel_scan(dev, oracle, K):
+    """K above 256^2 needs three scan levels."""
     rng = np.random.default_rng(5)
-    prob = W.random_problem(rng, 2, 65537, 2, n_squares=12)
-    _compare(_gpu(prob), oracle.solve(prob, want_U=True), name="K=65537")
+    prob = W.random_problem(rng, 2, K, 2, n_squares=12)
+    _compare(_gpu(prob), oracle.solve(prob, want_U=True), name=f"K={K}")
 
 
 @pytest.mark.parametrize("slices", [1, 2, 4, 8, 16])
