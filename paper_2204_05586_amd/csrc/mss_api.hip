@@ -360,6 +360,17 @@ mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
   M[0] = U;
   for (int l = 1; l <= lv.n_levels; ++l) M[l] = (const double*)(w + lv.agg_off[l]);
   hipError_t e;
+  if (lv.n_levels == 2 && (lv.n[1] + kScanTile - 1) / kScanTile <= 16) {
+    // level 0 up, levels 1-2 in one workgroup, level 0 down
+    e = launch_scan_reduce(N, M[0], lv.n[0], (double*)M[1], st);
+    if (e == hipSuccess)
+      e = launch_scan_top(N, M[1], lv.n[1], psi0, (double*)(w + lv.state_off[1]), st);
+    if (e == hipSuccess)
+      e = launch_scan_apply(N, M[0], lv.n[0], (const double*)(w + lv.state_off[1]), psi,
+                            psi_final, st);
+    if (e != hipSuccess) return api_hip_fail(e, "scan launch");
+    return api_ok();
+  }
   for (int l = 0; l < lv.n_levels; ++l) {
     e = launch_scan_reduce(N, M[l], lv.n[l], (double*)M[l + 1], st);
     if (e != hipSuccess) return api_hip_fail(e, "scan reduce launch");

@@ -51,6 +51,11 @@ hipError_t launch_scan_reduce(int N, const double* M, int64_t n, double* agg, hi
 hipError_t launch_scan_apply(int N, const double* M, int64_t n, const double* start, double* before,
                              double* after_last, hipStream_t st);
 
+// levels 1 and 2 of a two-level single-sequence scan in one workgroup
+// (n1 level-1 elements in at most 16 tiles)
+hipError_t launch_scan_top(int N, const double* M1, int64_t n1, const double* start,
+                           double* before1, hipStream_t st);
+
 hipError_t launch_spin_projection(int N, const double* psi, int64_t K, double* out,
                                   hipStream_t st);
 

@@ -39,6 +39,32 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const double* __restric
                 after_last);
 }
 
+// Levels 1 and 2 of a two-level scan in one workgroup (n1 <= 16 tiles):
+// wave w reduces level-1 tile w into LDS, wave 0 scans those aggregates
+// from start, then wave w applies its tile from the state entering it.  The
+// same tile routines on the same data as the separate launches, so the
+// result is bitwise the same; the LDS holds the level-2 aggregates and
+// entering states between the phases.
+constexpr int kTopWaves = 16;
+
+template <int N>
+__global__ void __launch_bounds__(64 * kTopWaves) scan_top_kernel(const double* __restrict__ M1,
+                                                                  int64_t n1,
+                                                                  const double* __restrict__ start,
+                                                                  double* __restrict__ before1) {
+  __shared__ double agg2[kTopWaves * 2 * N * N];
+  __shared__ double before2[kTopWaves * 2 * N];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n2 = (n1 + kScanTile - 1) / kScanTile;
+  tile_reduce<N, kScanPerLane>(M1, n1, wave, lane, agg2 + (size_t)wave * 2 * N * N);
+  __syncthreads();
+  if (wave == 0) tile_apply<N, kScanPerLane>(agg2, n2, 0, lane, true, start, before2, nullptr);
+  __syncthreads();
+  tile_apply<N, kScanPerLane>(M1, n1, wave, lane, true, before2 + (size_t)wave * 2 * N, before1,
+                              nullptr);
+}
+
 // <J_a> = psi^H J_a psi for one state per lane (a = x, y, z), written as
 // [K][3] doubles.  Spin-1/2: J = sigma/2; spin-1: J_x, J_y with 1/sqrt 2
 // couplings between neighbouring levels, J_z = diag(1, 0, -1).
@@ -114,6 +140,16 @@ hipError_t launch_scan_apply(int N, const double* M, int64_t n, const double* st
     hipLaunchKernelGGL(scan_apply_kernel<2>, grid, block, 0, st, M, n, start, before, after_last);
   else
     hipLaunchKernelGGL(scan_apply_kernel<3>, grid, block, 0, st, M, n, start, before, after_last);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_top(int N, const double* M1, int64_t n1, const double* start,
+                           double* before1, hipStream_t st) {
+  const int64_t tiles = (n1 + kScanTile - 1) / kScanTile;
+  if (tiles < 1 || tiles > kTopWaves) return hipErrorInvalidValue;
+  const dim3 grid(1), block((unsigned)(64 * tiles));
+  if (N == 2) hipLaunchKernelGGL(scan_top_kernel<2>, grid, block, 0, st, M1, n1, start, before1);
+  else hipLaunchKernelGGL(scan_top_kernel<3>, grid, block, 0, st, M1, n1, start, before1);
   return hipGetLastError();
 }
 
