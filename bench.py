@@ -57,10 +57,13 @@ def kernel_source_hash() -> str:
 
 
 def spin_one_flops_per_fine_step(tau: int) -> int:
-    """Algorithmic FP64 flops of one spin-1 CF4 fine step: two Lie-Trotter
-    exponentials of tau residual squarings (27 complex multiply-adds = 216
-    flops each) plus two 3x3 complex products into the interval operator."""
-    return 2 * tau * 216 + 2 * 216
+    """Algorithmic FP64 flops of one spin-1 CF4 fine step as computed: two
+    Lie-Trotter exponentials of tau residual squarings of a complex symmetric
+    3x3 matrix (six entries: 96 flops each, counting a fused multiply-add as
+    two) plus two general 3x3 complex products into the interval operator
+    (27 complex multiply-adds = 216 flops each).  Angle set-up and the
+    phases put back once per exponential are not counted."""
+    return 2 * tau * 96 + 2 * 216
 
 
 def cpu_baseline(problems, seconds: float) -> dict:

@@ -229,23 +229,41 @@ __device__ __forceinline__ void exp_half(const double th[4], int /*tau*/, Mat<2>
 // ---------------------------------------------------------------------------
 // spin-1 Lie-Trotter exponential (Sec. "Lie-Trotter based exponentiator")
 // ---------------------------------------------------------------------------
-// Residual a = T - I of T = exp(-iD/2) exp(-i Phi J_phi) exp(-iD/2) with
-// z = theta_z / n, q = theta_q / n, Phi = |theta_xy| / n, n = 2^tau,
-// written entry by entry (element-wise form of the paper with the T_13 and
-// T_22 misprints corrected); diagonals as (e^{i b} - 1) - k S^2 e^{i b} with
-// e^{i b} - 1 = -2 sin^2(b/2) + i sin b, so nothing cancels.
-__device__ __forceinline__ void lie_trotter_residual(const double th[4], int tau, Mat<3>& a) {
+// T = exp(-iD/2) exp(-i Phi J_phi) exp(-iD/2) with z = theta_z / n,
+// q = theta_q / n, Phi = |theta_xy| / n, n = 2^tau (the symmetric split of
+// the spin-1 Lie-Trotter step).  With P = diag(e^{-i phi}, 1, e^{i phi}),
+// exp(-i Phi J_phi) = P exp(-i Phi J_x) P^H and P commutes with D, so
+// T = P T' P^H where T' is the same split at phi = 0.  T' is complex
+// symmetric (J_x real symmetric, D diagonal), and so is every residual
+// squaring of it (a polynomial in the residual); T^(2^tau) = P T'^(2^tau) P^H.
+// The squarings therefore run on the six entries on and above the diagonal
+// and the phases e^{-i phi (m_j - m_k)}, m = (1, 0, -1), are put back once.
+//
+// Complex symmetric 3x3 residual: entries 0..2 the diagonal, 3 = (0,1),
+// 4 = (0,2), 5 = (1,2).
+struct Sym3 {
+  double r[6], i[6];
+};
+
+// Residual a' = T' - I, written entry by entry (element-wise form of the
+// paper at phi = 0, the T_13 and T_22 misprints corrected); diagonals as
+// (e^{i b} - 1) - k S^2 e^{i b} with e^{i b} - 1 = -2 sin^2(b/2) + i sin b,
+// so nothing cancels.  Returns e^{i phi} = (theta_x + i theta_y) / rho.
+__device__ __forceinline__ void lie_trotter_residual(const double th[4], int tau, Sym3& a,
+                                                     double* ep_r, double* ep_i) {
   const double ninv = ldexp(1.0, -tau);
   const double z = th[2] * ninv;
   const double q = th[3] * ninv;
   const double rho = sqrt(fma(th[0], th[0], th[1] * th[1]));  // angles are far from overflow
   const double Phi = rho * ninv;
-  double epr = 1.0, epi = 0.0;  // e^{i phi} = (theta_x + i theta_y) / rho
+  double epr = 1.0, epi = 0.0;
   if (rho > 0.0) {
     const double inv = 1.0 / rho;
     epr = th[0] * inv;
     epi = th[1] * inv;
   }
+  *ep_r = epr;
+  *ep_i = epi;
   double S, C;
   sincos_small(0.5 * Phi, &S, &C);
   const double S2 = S * S;
@@ -256,23 +274,13 @@ __device__ __forceinline__ void lie_trotter_residual(const double th[4], int tau
   // g = e^{iq/6} e^{-iz/2}, h = e^{iq/6} e^{iz/2}
   const double gr = fma(cq, cz, sq * sz), gi = fma(sq, cz, -cq * sz);
   const double hr = fma(cq, cz, -sq * sz), hi = fma(sq, cz, cq * sz);
-  // x * e^{-/+ i phi}
-  const double gmr = fma(gr, epr, gi * epi), gmi = fma(gi, epr, -gr * epi);
-  const double gpr = fma(gr, epr, -gi * epi), gpi = fma(gi, epr, gr * epi);
-  const double hmr = fma(hr, epr, hi * epi), hmi = fma(hi, epr, -hr * epi);
-  const double hpr = fma(hr, epr, -hi * epi), hpi = fma(hi, epr, hr * epi);
-  // (-i rs) (x + i y) = rs y - i rs x
-  a.r[0][1] = rs * gmi;  a.i[0][1] = -rs * gmr;
-  a.r[1][0] = rs * gpi;  a.i[1][0] = -rs * gpr;
-  a.r[1][2] = rs * hmi;  a.i[1][2] = -rs * hmr;
-  a.r[2][1] = rs * hpi;  a.i[2][1] = -rs * hpr;
-  // T_13 = -S^2 e^{-iq/3} e^{-2i phi}, T_31 = -S^2 e^{-iq/3} e^{2i phi}
-  const double e3r = fma(cq, cq, -sq * sq), e3i = -2.0 * sq * cq;  // e^{-iq/3}
-  const double e2r = fma(epr, epr, -epi * epi), e2i = 2.0 * epr * epi;  // e^{2i phi}
-  a.r[0][2] = -S2 * fma(e3r, e2r, e3i * e2i);
-  a.i[0][2] = -S2 * fma(e3i, e2r, -e3r * e2i);
-  a.r[2][0] = -S2 * fma(e3r, e2r, -e3i * e2i);
-  a.i[2][0] = -S2 * fma(e3i, e2r, e3r * e2i);
+  // T'_12 = -i rs g, T'_23 = -i rs h; (-i rs) (x + i y) = rs y - i rs x
+  a.r[3] = rs * gi;  a.i[3] = -rs * gr;
+  a.r[5] = rs * hi;  a.i[5] = -rs * hr;
+  // T'_13 = -S^2 e^{-iq/3}
+  const double e3r = fma(cq, cq, -sq * sq), e3i = -2.0 * sq * cq;
+  a.r[4] = -S2 * e3r;
+  a.i[4] = -S2 * e3i;
   // diagonals, b1 = -z - q/3, b2 = 2q/3, b3 = z - q/3: the half-angle
   // exponentials e^{i b_j / 2} are conj(h), conj(e^{-iq/3}) and conj(g)
   const double shv[3] = {-hi, -e3i, -gi};  // sin(b_j / 2)
@@ -283,38 +291,98 @@ __device__ __forceinline__ void lie_trotter_residual(const double th[4], int tau
     const double sh = shv[j], ch = chv[j];
     const double mr = -2.0 * sh * sh;  // Re(e^{ib} - 1)
     const double mi = 2.0 * sh * ch;   // Im = sin b
-    a.r[j][j] = fma(-k[j], 1.0 + mr, mr);
-    a.i[j][j] = fma(-k[j], mi, mi);
+    a.r[j] = fma(-k[j], 1.0 + mr, mr);
+    a.i[j] = fma(-k[j], mi, mi);
   }
 }
 
-// One residual squaring y = (x + 2I) x: only the real diagonal of the
-// left factor differs from x.
-__device__ __forceinline__ void residual_square(const Mat<3>& x, Mat<3>& y) {
-  Mat<3> b = x;
-  b.r[0][0] += 2.0;
-  b.r[1][1] += 2.0;
-  b.r[2][2] += 2.0;
-  matmul<3>(b, x, y);
+// One residual squaring y = (x + 2I) x of a complex symmetric x:
+//   y_jj = (x_jj + 2) x_jj + x_jk^2 + x_jl^2
+//   y_jk = x_jk (x_jj + 2 + x_kk) + x_jl x_kl        ({j, k, l} = {0, 1, 2})
+// 63 instructions where the general 3x3 product takes 111.
+__device__ __forceinline__ void residual_square(const Sym3& x, Sym3& y) {
+  const double b0 = x.r[0] + 2.0, b1 = x.r[1] + 2.0, b2 = x.r[2] + 2.0;
+  // squares of the off-diagonal entries
+  double sr[3], si[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    const double xr = x.r[3 + o], xi = x.i[3 + o];
+    const double t = xr * xi;
+    sr[o] = fma(xr, xr, -xi * xi);
+    si[o] = t + t;
+  }
+  // diagonal j adds the squares of the two off-diagonal entries in its row:
+  // row 0: (0,1), (0,2); row 1: (0,1), (1,2); row 2: (0,2), (1,2)
+  {
+    const double ar = sr[0] + sr[1], ai = si[0] + si[1];
+    y.r[0] = fma(b0, x.r[0], fma(-x.i[0], x.i[0], ar));
+    y.i[0] = fma(b0, x.i[0], fma(x.i[0], x.r[0], ai));
+  }
+  {
+    const double ar = sr[0] + sr[2], ai = si[0] + si[2];
+    y.r[1] = fma(b1, x.r[1], fma(-x.i[1], x.i[1], ar));
+    y.i[1] = fma(b1, x.i[1], fma(x.i[1], x.r[1], ai));
+  }
+  {
+    const double ar = sr[1] + sr[2], ai = si[1] + si[2];
+    y.r[2] = fma(b2, x.r[2], fma(-x.i[2], x.i[2], ar));
+    y.i[2] = fma(b2, x.i[2], fma(x.i[2], x.r[2], ai));
+  }
+  // (0,1) = x01 (x00 + 2 + x11) + x02 x12
+  {
+    const double cr = b0 + x.r[1], ci = x.i[0] + x.i[1];
+    y.r[3] = fma(x.r[3], cr, fma(-x.i[3], ci, fma(x.r[4], x.r[5], -x.i[4] * x.i[5])));
+    y.i[3] = fma(x.r[3], ci, fma(x.i[3], cr, fma(x.r[4], x.i[5], x.i[4] * x.r[5])));
+  }
+  // (0,2) = x02 (x00 + 2 + x22) + x01 x12
+  {
+    const double cr = b0 + x.r[2], ci = x.i[0] + x.i[2];
+    y.r[4] = fma(x.r[4], cr, fma(-x.i[4], ci, fma(x.r[3], x.r[5], -x.i[3] * x.i[5])));
+    y.i[4] = fma(x.r[4], ci, fma(x.i[4], cr, fma(x.r[3], x.i[5], x.i[3] * x.r[5])));
+  }
+  // (1,2) = x12 (x11 + 2 + x22) + x01 x02
+  {
+    const double cr = b1 + x.r[2], ci = x.i[1] + x.i[2];
+    y.r[5] = fma(x.r[5], cr, fma(-x.i[5], ci, fma(x.r[3], x.r[4], -x.i[3] * x.i[4])));
+    y.i[5] = fma(x.r[5], ci, fma(x.i[5], cr, fma(x.r[3], x.i[4], x.i[3] * x.r[4])));
+  }
 }
 
-// tau residual squarings a <- (a + 2I) a, then I + a.  Two squarings per
-// trip alternate between two register sets, so nothing is copied.
+// tau residual squarings a' <- (a' + 2I) a' (two per trip, alternating
+// between two register sets, so nothing is copied), then
+// E = P (I + a') P^H.
 __device__ __forceinline__ void exp_one(const double th[4], int tau, Mat<3>& E) {
-  Mat<3> a;
-  lie_trotter_residual(th, tau, a);
+  Sym3 a, b;
+  double epr, epi;
+  lie_trotter_residual(th, tau, a, &epr, &epi);
   for (int s = 0; s + 2 <= tau; s += 2) {
-    residual_square(a, E);
-    residual_square(E, a);
+    residual_square(a, b);
+    residual_square(b, a);
   }
   if (tau & 1) {
-    residual_square(a, E);
-    a = E;
+    residual_square(a, b);
+    a = b;
   }
-  E = a;
-  E.r[0][0] += 1.0;
-  E.r[1][1] += 1.0;
-  E.r[2][2] += 1.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    E.r[j][j] = a.r[j] + 1.0;
+    E.i[j][j] = a.i[j];
+  }
+  // (0,1), (1,2) carry e^{-i phi}, (1,0), (2,1) carry e^{i phi}
+  E.r[0][1] = fma(a.r[3], epr, a.i[3] * epi);
+  E.i[0][1] = fma(a.i[3], epr, -a.r[3] * epi);
+  E.r[1][0] = fma(a.r[3], epr, -a.i[3] * epi);
+  E.i[1][0] = fma(a.i[3], epr, a.r[3] * epi);
+  E.r[1][2] = fma(a.r[5], epr, a.i[5] * epi);
+  E.i[1][2] = fma(a.i[5], epr, -a.r[5] * epi);
+  E.r[2][1] = fma(a.r[5], epr, -a.i[5] * epi);
+  E.i[2][1] = fma(a.i[5], epr, a.r[5] * epi);
+  // (0,2) carries e^{-2i phi}, (2,0) carries e^{2i phi}
+  const double e2r = fma(epr, epr, -epi * epi), e2i = 2.0 * epr * epi;
+  E.r[0][2] = fma(a.r[4], e2r, a.i[4] * e2i);
+  E.i[0][2] = fma(a.i[4], e2r, -a.r[4] * e2i);
+  E.r[2][0] = fma(a.r[4], e2r, -a.i[4] * e2i);
+  E.i[2][0] = fma(a.i[4], e2r, a.r[4] * e2i);
 }
 
 template <int N> struct Exponentiator;

@@ -101,7 +101,7 @@ def test_server_overlaps_requests(torch_dev):
     are admitted into the running rounds and finish before it, instead of
     waiting behind it."""
     from paper_2204_05586_amd import native
-    long_p = W.spin_one_sensing(n_samples=300_000, t_start=0.0)
+    long_p = W.spin_one_sensing(n_samples=3_000_000, t_start=0.0)
     short = _mix(20, seed=32, k_hi=5e3)
     srv = native.Server(iteration_steps=2e5)
     t_long = srv.submit(long_p)
