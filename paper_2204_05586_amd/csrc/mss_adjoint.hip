@@ -29,182 +29,148 @@
 namespace mss {
 
 // ---------------------------------------------------------------------------
-// two-direction dual numbers for the exponentiator set-up: v + x e_x + y e_y
-// with e_x, e_y nilpotent; x and y carry d / d theta_x and d / d theta_y
+// spin-1 exponential with its derivatives along theta_x and theta_y.
+//
+// E = P(phi) E'(rho) P(phi)^H (exp_one): the symmetric factor E' depends on
+// theta_x, theta_y only through rho = |theta_xy| and the phases only through
+// phi.  So one tangent direction, d/d rho, goes through the squarings (the
+// tangent of a symmetric residual is symmetric too), the phi derivative is
+// closed form, dE_jk/d phi = -i (m_j - m_k) E_jk, and
+//   dE/dtheta_x = cos(phi) dE/drho - (sin(phi) / rho) dE/dphi,
+//   dE/dtheta_y = sin(phi) dE/drho + (cos(phi) / rho) dE/dphi.
+// Both derivatives are taken as 0 at rho = 0.
 // ---------------------------------------------------------------------------
-struct D2 {
-  double v, x, y;
-};
-__device__ __forceinline__ D2 operator+(D2 a, D2 b) { return {a.v + b.v, a.x + b.x, a.y + b.y}; }
-__device__ __forceinline__ D2 operator-(D2 a, D2 b) { return {a.v - b.v, a.x - b.x, a.y - b.y}; }
-__device__ __forceinline__ D2 operator-(D2 a) { return {-a.v, -a.x, -a.y}; }
-__device__ __forceinline__ D2 operator*(D2 a, D2 b) {
-  return {a.v * b.v, fma(a.x, b.v, a.v * b.x), fma(a.y, b.v, a.v * b.y)};
-}
-__device__ __forceinline__ D2 operator*(double a, D2 b) { return {a * b.v, a * b.x, a * b.y}; }
-__device__ __forceinline__ D2 operator+(D2 a, double b) { return {a.v + b, a.x, a.y}; }
-__device__ __forceinline__ void sincos_d2(D2 t, D2* s, D2* c) {
-  double sv, cv;
-  sincos_small(t.v, &sv, &cv);
-  *s = {sv, cv * t.x, cv * t.y};
-  *c = {cv, -sv * t.x, -sv * t.y};
-}
 
-struct CD2 {
-  D2 r, i;
-};
-__device__ __forceinline__ CD2 cmul(CD2 a, CD2 b) {
-  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
-}
-__device__ __forceinline__ CD2 conj(CD2 a) { return {a.r, -a.i}; }
-
-// Residual a = T - I and its derivatives along theta_x (dax) and theta_y
-// (day): the entries of lie_trotter_residual in dual arithmetic.  The
-// derivative of e^{i phi} is taken as 0 at rho = 0.
-__device__ __forceinline__ void lie_trotter_residual_tangent(const double th[4], int tau, Mat<3>& a,
-                                                             Mat<3>& dax, Mat<3>& day) {
+// d a' / d rho of the residual of lie_trotter_residual, term by term from
+// the same expressions (a' depends on rho only through Phi = rho / n).
+__device__ __forceinline__ void lie_trotter_residual_drho(const double th[4], int tau, Sym3& da) {
   const double ninv = ldexp(1.0, -tau);
-  const D2 tx = {th[0], 1.0, 0.0}, ty = {th[1], 0.0, 1.0};
-  const D2 z = {th[2] * ninv, 0.0, 0.0};
-  const D2 q = {th[3] * ninv, 0.0, 0.0};
-  const double rv = sqrt(fma(th[0], th[0], th[1] * th[1]));
-  D2 rho = {rv, 0.0, 0.0};
-  CD2 ep = {{1.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};  // e^{i phi}
-  if (rv > 0.0) {
-    const double inv = 1.0 / rv;
-    rho.x = th[0] * inv;
-    rho.y = th[1] * inv;
-    const D2 rinv = {inv, -rho.x * inv * inv, -rho.y * inv * inv};
-    ep = {tx * rinv, ty * rinv};
-  }
-  const D2 Phi = ninv * rho;
-  D2 S, C;
-  sincos_d2(0.5 * Phi, &S, &C);
-  const D2 S2 = S * S;
-  const D2 rs = kRsqrt2 * (2.0 * (S * C));
-  D2 sz, cz, sq, cq;
-  sincos_d2(0.5 * z, &sz, &cz);
-  sincos_d2((1.0 / 6.0) * q, &sq, &cq);
-  const CD2 eq = {cq, sq}, ez = {cz, sz};
-  const CD2 g = cmul(eq, conj(ez)), h = cmul(eq, ez);
-  const CD2 em = conj(ep);
-  const CD2 gm = cmul(g, em), gp = cmul(g, ep), hm = cmul(h, em), hp = cmul(h, ep);
-  // (-i rs) (x + i y) = rs y - i rs x
-  const CD2 off[4] = {gm, gp, hm, hp};
-  const int oi[4] = {0, 1, 1, 2}, oj[4] = {1, 0, 2, 1};
-#pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    const D2 re = rs * off[n].i, im = -(rs * off[n].r);
-    a.r[oi[n]][oj[n]] = re.v;
-    a.i[oi[n]][oj[n]] = im.v;
-    dax.r[oi[n]][oj[n]] = re.x;
-    dax.i[oi[n]][oj[n]] = im.x;
-    day.r[oi[n]][oj[n]] = re.y;
-    day.i[oi[n]][oj[n]] = im.y;
-  }
-  const CD2 e3 = conj(cmul(eq, eq));  // e^{-iq/3}
-  const CD2 e2 = cmul(ep, ep);        // e^{2i phi}
-  const CD2 t13 = cmul(e3, conj(e2)), t31 = cmul(e3, e2);
-  const D2 mS2 = -S2;
-  const D2 c02r = mS2 * t13.r, c02i = mS2 * t13.i, c20r = mS2 * t31.r, c20i = mS2 * t31.i;
-  a.r[0][2] = c02r.v;  dax.r[0][2] = c02r.x;  day.r[0][2] = c02r.y;
-  a.i[0][2] = c02i.v;  dax.i[0][2] = c02i.x;  day.i[0][2] = c02i.y;
-  a.r[2][0] = c20r.v;  dax.r[2][0] = c20r.x;  day.r[2][0] = c20r.y;
-  a.i[2][0] = c20i.v;  dax.i[2][0] = c20i.x;  day.i[2][0] = c20i.y;
-  // diagonals: half-angle exponentials e^{i b_j / 2} = conj(h), conj(e3), conj(g)
-  // for b = (-z - q/3, 2q/3, z - q/3)
-  const D2 shv[3] = {-h.i, -e3.i, -g.i};
-  const D2 chv[3] = {h.r, e3.r, g.r};
-  const D2 k[3] = {S2, 2.0 * S2, S2};
+  const double z = th[2] * ninv;
+  const double q = th[3] * ninv;
+  const double rho = sqrt(fma(th[0], th[0], th[1] * th[1]));
+  const double Phi = rho * ninv;
+  double S, C;
+  sincos_small(0.5 * Phi, &S, &C);
+  const double dS = 0.5 * ninv * C, dC = -0.5 * ninv * S;
+  const double dS2 = 2.0 * S * dS;
+  const double drs = kRsqrt2 * (2.0 * fma(dS, C, S * dC));
+  double sz, cz, sq, cq;
+  sincos_small(0.5 * z, &sz, &cz);
+  sincos_small(q * (1.0 / 6.0), &sq, &cq);
+  const double gr = fma(cq, cz, sq * sz), gi = fma(sq, cz, -cq * sz);
+  const double hr = fma(cq, cz, -sq * sz), hi = fma(sq, cz, cq * sz);
+  da.r[3] = drs * gi;  da.i[3] = -drs * gr;
+  da.r[5] = drs * hi;  da.i[5] = -drs * hr;
+  const double e3r = fma(cq, cq, -sq * sq), e3i = -2.0 * sq * cq;
+  da.r[4] = -dS2 * e3r;
+  da.i[4] = -dS2 * e3i;
+  // diagonals (e^{i b} - 1) - k S^2 e^{i b}: only k S^2 depends on rho
+  const double shv[3] = {-hi, -e3i, -gi};
+  const double chv[3] = {hr, e3r, gr};
+  const double dk[3] = {dS2, 2.0 * dS2, dS2};
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const D2 sh = shv[j], ch = chv[j];
-    const D2 mr = -2.0 * (sh * sh);
-    const D2 mi = 2.0 * (sh * ch);
-    const D2 re = mr - k[j] * (mr + 1.0);
-    const D2 im = mi - k[j] * mi;
-    a.r[j][j] = re.v;  dax.r[j][j] = re.x;  day.r[j][j] = re.y;
-    a.i[j][j] = im.v;  dax.i[j][j] = im.x;  day.i[j][j] = im.y;
+    const double sh = shv[j], ch = chv[j];
+    const double mr = -2.0 * sh * sh;
+    const double mi = 2.0 * sh * ch;
+    da.r[j] = -dk[j] * (1.0 + mr);
+    da.i[j] = -dk[j] * mi;
   }
 }
 
-// C += A * B
-template <int N>
-__device__ __forceinline__ void matmul_add(const Mat<N>& A, const Mat<N>& B, Mat<N>& C) {
+// index of entry (j, k) of a Sym3
+__device__ __forceinline__ constexpr int sym_index(int j, int k) { return j == k ? j : 2 + j + k; }
+
+// Tangent of one residual squaring: for a' <- (a' + 2I) a', the tangent d
+// goes to d (a' + I) + (a' + I) d = M + M^T with M = d (a' + I), which is
+// symmetric like d: entries M_jk + M_kj, and 2 M_jj on the diagonal.
+__device__ __forceinline__ void tangent_square(const Sym3& a, const Sym3& d, Sym3& dn) {
+  double br[6], bi[6];  // a' + I
 #pragma unroll
-  for (int x = 0; x < N; ++x)
+  for (int n = 0; n < 6; ++n) {
+    br[n] = n < 3 ? a.r[n] + 1.0 : a.r[n];
+    bi[n] = a.i[n];
+  }
 #pragma unroll
-    for (int y = 0; y < N; ++y) {
-      double re = C.r[x][y], im = C.i[x][y];
+  for (int j = 0; j < 3; ++j)
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        re = fma(A.r[x][k], B.r[k][y], re);
-        re = fma(-A.i[x][k], B.i[k][y], re);
-        im = fma(A.r[x][k], B.i[k][y], im);
-        im = fma(A.i[x][k], B.r[k][y], im);
+    for (int k = j; k < 3; ++k) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const int x = sym_index(j, l), y = sym_index(l, k);
+        re = fma(d.r[x], br[y], re);
+        re = fma(-d.i[x], bi[y], re);
+        im = fma(d.r[x], bi[y], im);
+        im = fma(d.i[x], br[y], im);
       }
-      C.r[x][y] = re;
-      C.i[x][y] = im;
+      const int o = sym_index(j, k);
+      if (j == k) {
+        dn.r[o] = 2.0 * re;
+        dn.i[o] = 2.0 * im;
+      } else {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const int x = sym_index(k, l), y = sym_index(l, j);
+          re = fma(d.r[x], br[y], re);
+          re = fma(-d.i[x], bi[y], re);
+          im = fma(d.r[x], bi[y], im);
+          im = fma(d.i[x], br[y], im);
+        }
+        dn.r[o] = re;
+        dn.i[o] = im;
+      }
     }
 }
 
-// One tangent residual squaring of (a, dx, dy) with b = a + 2I:
-//   dx' = dx a + b dx  -> f,   dy' = dy a + b dy  -> dx,   a' = b a  -> dy,
-// each written only after the matrix it overwrites is no longer read.  The
-// new state (a', dx', dy') is (dy, f, dx) and a is free: four register sets
-// rotate, so no matrix is copied.
-__device__ __forceinline__ void tangent_step(const Mat<3>& a, Mat<3>& dx, Mat<3>& dy, Mat<3>& f) {
-  Mat<3> b = a;
-  b.r[0][0] += 2.0;
-  b.r[1][1] += 2.0;
-  b.r[2][2] += 2.0;
-  matmul<3>(dx, a, f);
-  matmul_add<3>(b, dx, f);
-  matmul<3>(dy, a, dx);
-  matmul_add<3>(b, dy, dx);
-  matmul<3>(b, a, dy);
-}
-
 // E = exp of the step angles (Lie-Trotter, tau residual squarings) with
-// dE/dtheta_x and dE/dtheta_y: the derivatives of exactly the computed E.
-__device__ __forceinline__ void exp_one_tangent(const double th[4], int tau, Mat<3>& E,
-                                                Mat<3>& dEx, Mat<3>& dEy) {
-  Mat<3> A, X, Y, F;
-  lie_trotter_residual_tangent(th, tau, A, X, Y);
+// G = dE/drho, the derivative of exactly the computed E, and the chain
+// coefficients c = (d rho / d theta_x, d rho / d theta_y, d phi / d theta_x,
+// d phi / d theta_y), all 0 at rho = 0.
+__device__ __forceinline__ void exp_one_tangent(const double th[4], int tau, Mat<3>& E, Mat<3>& G,
+                                                double c[4]) {
+  // Three register sets rotate: a step reads (a, d) and writes the new
+  // tangent over the free set, then the new residual over d, which the
+  // tangent no longer needs; three steps bring the roles back.
+  Sym3 X, Y, Z;
+  double epr, epi;
+  lie_trotter_residual(th, tau, X, &epr, &epi);
+  lie_trotter_residual_drho(th, tau, Y);
   int s = 0;
-  for (; s + 4 <= tau; s += 4) {  // four steps bring the roles back to (A, X, Y)
-    tangent_step(A, X, Y, F);     // state (Y, F, X)
-    tangent_step(Y, F, X, A);     // state (X, A, F)
-    tangent_step(X, A, F, Y);     // state (F, Y, A)
-    tangent_step(F, Y, A, X);     // state (A, X, Y)
+  for (; s + 3 <= tau; s += 3) {
+    tangent_square(X, Y, Z);  // (a, d) = (X, Y)
+    residual_square(X, Y);
+    tangent_square(Y, Z, X);  // (a, d) = (Y, Z)
+    residual_square(Y, Z);
+    tangent_square(Z, X, Y);  // (a, d) = (Z, X)
+    residual_square(Z, X);
   }
   const int r = tau - s;
   if (r == 0) {
-    E = A;
-    dEx = X;
-    dEy = Y;
+    sym_to_full(X, 1.0, epr, epi, E);
+    sym_to_full(Y, 0.0, epr, epi, G);
   } else if (r == 1) {
-    tangent_step(A, X, Y, F);
-    E = Y;
-    dEx = F;
-    dEy = X;
-  } else if (r == 2) {
-    tangent_step(A, X, Y, F);
-    tangent_step(Y, F, X, A);
-    E = X;
-    dEx = A;
-    dEy = F;
+    tangent_square(X, Y, Z);
+    residual_square(X, Y);
+    sym_to_full(Y, 1.0, epr, epi, E);
+    sym_to_full(Z, 0.0, epr, epi, G);
   } else {
-    tangent_step(A, X, Y, F);
-    tangent_step(Y, F, X, A);
-    tangent_step(X, A, F, Y);
-    E = F;
-    dEx = Y;
-    dEy = A;
+    tangent_square(X, Y, Z);
+    residual_square(X, Y);
+    tangent_square(Y, Z, X);
+    residual_square(Y, Z);
+    sym_to_full(Z, 1.0, epr, epi, E);
+    sym_to_full(X, 0.0, epr, epi, G);
   }
-  E.r[0][0] += 1.0;
-  E.r[1][1] += 1.0;
-  E.r[2][2] += 1.0;
+  const double rho = sqrt(fma(th[0], th[0], th[1] * th[1]));
+  c[0] = c[1] = c[2] = c[3] = 0.0;
+  if (rho > 0.0) {
+    const double inv = 1.0 / rho;
+    c[0] = epr;
+    c[1] = epi;
+    c[2] = -epi * inv;
+    c[3] = epr * inv;
+  }
 }
 
 // Spin-1/2: E = cos(|theta|/2) I - i (sin(|theta|/2)/|theta|) theta.sigma and
@@ -246,20 +212,6 @@ __device__ __forceinline__ void exp_half_tangent(const double th[4], int /*tau*/
     dE.r[1][1] = dc;   dE.i[1][1] = dz;
   }
 }
-
-template <int N> struct TangentExp;
-template <> struct TangentExp<2> {
-  static __device__ __forceinline__ void apply(const double th[4], int tau, Mat<2>& E,
-                                               Mat<2>& dEx, Mat<2>& dEy) {
-    exp_half_tangent(th, tau, E, dEx, dEy);
-  }
-};
-template <> struct TangentExp<3> {
-  static __device__ __forceinline__ void apply(const double th[4], int tau, Mat<3>& E,
-                                               Mat<3>& dEx, Mat<3>& dEy) {
-    exp_one_tangent(th, tau, E, dEx, dEy);
-  }
-};
 
 // ---------------------------------------------------------------------------
 // small vector helpers
@@ -303,6 +255,57 @@ __device__ __forceinline__ double bilinear(const double* lr, const double* li, c
   }
   return 2.0 * acc;
 }
+
+// 2 Re(l^H (dE/dphi) x) with dE/dphi = -i w E, w_jk = m_j - m_k = k - j:
+// Re(conj(l_j) (-i) w E_jk x_k) = w (lr Im(E_jk x_k) - li Re(E_jk x_k)).
+__device__ __forceinline__ double bilinear_phi(const double* lr, const double* li, const Mat<3>& E,
+                                               const double* xr, const double* xi) {
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (a == b) continue;
+      const double er = fma(E.r[a][b], xr[b], -E.i[a][b] * xi[b]);
+      const double ei = fma(E.r[a][b], xi[b], E.i[a][b] * xr[b]);
+      acc = fma((double)(b - a), fma(lr[a], ei, -li[a] * er), acc);
+    }
+  return 2.0 * acc;
+}
+
+// One exponential of the backward replay: from the state after it (p) and
+// the costate after it (l), the state before it b = E^H p, the costate
+// before it nl = E^H l, and g = dloss/dtheta_{x,y} = 2 Re(l^H dE/dtheta b).
+template <int N> struct TangentStep;
+template <> struct TangentStep<2> {
+  static __device__ __forceinline__ void apply(const double th[4], int tau, const double* lr,
+                                               const double* li, const double* pr,
+                                               const double* pi, double* br, double* bi,
+                                               double* nlr, double* nli, double* gx, double* gy) {
+    Mat<2> E, dEx, dEy;
+    exp_half_tangent(th, tau, E, dEx, dEy);
+    mat_h_vec<2>(E, pr, pi, br, bi);
+    *gx = bilinear<2>(lr, li, dEx, br, bi);
+    *gy = bilinear<2>(lr, li, dEy, br, bi);
+    mat_h_vec<2>(E, lr, li, nlr, nli);
+  }
+};
+template <> struct TangentStep<3> {
+  static __device__ __forceinline__ void apply(const double th[4], int tau, const double* lr,
+                                               const double* li, const double* pr,
+                                               const double* pi, double* br, double* bi,
+                                               double* nlr, double* nli, double* gx, double* gy) {
+    Mat<3> E, G;
+    double c[4];
+    exp_one_tangent(th, tau, E, G, c);
+    mat_h_vec<3>(E, pr, pi, br, bi);
+    const double grho = bilinear<3>(lr, li, G, br, bi);
+    const double gphi = bilinear_phi(lr, li, E, br, bi);
+    *gx = fma(c[0], grho, c[2] * gphi);
+    *gy = fma(c[1], grho, c[3] * gphi);
+    mat_h_vec<3>(E, lr, li, nlr, nli);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // adjoint kernel
@@ -421,14 +424,9 @@ __device__ __forceinline__ void adjoint_interval(const AdjArgs& A, const AdjDesc
     cf4_angles(terms, s.params, tk, l, s.dt, wr, rot, th[0], th[1]);
     double gx[2], gy[2];
     for (int e = 1; e >= 0; --e) {
-      Mat<N> E, dEx, dEy;
-      // E with dE/dtheta_x and dE/dtheta_y; the state before E and the new costate
-      TangentExp<N>::apply(th[e], s.tau, E, dEx, dEy);
+      // the state before E, the new costate and the angle derivatives
       double br[N], bi[N], nlr[N], nli[N];
-      mat_h_vec<N>(E, pr, pi, br, bi);
-      gx[e] = bilinear<N>(lr, li, dEx, br, bi);
-      gy[e] = bilinear<N>(lr, li, dEy, br, bi);
-      mat_h_vec<N>(E, lr, li, nlr, nli);
+      TangentStep<N>::apply(th[e], s.tau, lr, li, pr, pi, br, bi, nlr, nli, &gx[e], &gy[e]);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         pr[a] = br[a];

@@ -348,6 +348,33 @@ __device__ __forceinline__ void residual_square(const Sym3& x, Sym3& y) {
   }
 }
 
+// M = P (s + d I) P^H for a complex symmetric s: the off-diagonal entries
+// take the phases e^{-i phi (m_j - m_k)}, m = (1, 0, -1), of
+// e^{i phi} = (epr, epi); d is added to the real diagonal.
+__device__ __forceinline__ void sym_to_full(const Sym3& s, double d, double epr, double epi,
+                                            Mat<3>& M) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    M.r[j][j] = s.r[j] + d;
+    M.i[j][j] = s.i[j];
+  }
+  // (0,1), (1,2) carry e^{-i phi}, (1,0), (2,1) carry e^{i phi}
+  M.r[0][1] = fma(s.r[3], epr, s.i[3] * epi);
+  M.i[0][1] = fma(s.i[3], epr, -s.r[3] * epi);
+  M.r[1][0] = fma(s.r[3], epr, -s.i[3] * epi);
+  M.i[1][0] = fma(s.i[3], epr, s.r[3] * epi);
+  M.r[1][2] = fma(s.r[5], epr, s.i[5] * epi);
+  M.i[1][2] = fma(s.i[5], epr, -s.r[5] * epi);
+  M.r[2][1] = fma(s.r[5], epr, -s.i[5] * epi);
+  M.i[2][1] = fma(s.i[5], epr, s.r[5] * epi);
+  // (0,2) carries e^{-2i phi}, (2,0) carries e^{2i phi}
+  const double e2r = fma(epr, epr, -epi * epi), e2i = 2.0 * epr * epi;
+  M.r[0][2] = fma(s.r[4], e2r, s.i[4] * e2i);
+  M.i[0][2] = fma(s.i[4], e2r, -s.r[4] * e2i);
+  M.r[2][0] = fma(s.r[4], e2r, -s.i[4] * e2i);
+  M.i[2][0] = fma(s.i[4], e2r, s.r[4] * e2i);
+}
+
 // tau residual squarings a' <- (a' + 2I) a' (two per trip, alternating
 // between two register sets, so nothing is copied), then
 // E = P (I + a') P^H.
@@ -363,26 +390,7 @@ __device__ __forceinline__ void exp_one(const double th[4], int tau, Mat<3>& E) 
     residual_square(a, b);
     a = b;
   }
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    E.r[j][j] = a.r[j] + 1.0;
-    E.i[j][j] = a.i[j];
-  }
-  // (0,1), (1,2) carry e^{-i phi}, (1,0), (2,1) carry e^{i phi}
-  E.r[0][1] = fma(a.r[3], epr, a.i[3] * epi);
-  E.i[0][1] = fma(a.i[3], epr, -a.r[3] * epi);
-  E.r[1][0] = fma(a.r[3], epr, -a.i[3] * epi);
-  E.i[1][0] = fma(a.i[3], epr, a.r[3] * epi);
-  E.r[1][2] = fma(a.r[5], epr, a.i[5] * epi);
-  E.i[1][2] = fma(a.i[5], epr, -a.r[5] * epi);
-  E.r[2][1] = fma(a.r[5], epr, -a.i[5] * epi);
-  E.i[2][1] = fma(a.i[5], epr, a.r[5] * epi);
-  // (0,2) carries e^{-2i phi}, (2,0) carries e^{2i phi}
-  const double e2r = fma(epr, epr, -epi * epi), e2i = 2.0 * epr * epi;
-  E.r[0][2] = fma(a.r[4], e2r, a.i[4] * e2i);
-  E.i[0][2] = fma(a.i[4], e2r, -a.r[4] * e2i);
-  E.r[2][0] = fma(a.r[4], e2r, -a.i[4] * e2i);
-  E.i[2][0] = fma(a.i[4], e2r, a.r[4] * e2i);
+  sym_to_full(a, 1.0, epr, epi, E);
 }
 
 template <int N> struct Exponentiator;
