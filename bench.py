@@ -35,9 +35,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # sources are unchanged.
 MEASURED_TRAFFIC = {
     ("batch_integrate_kernel", "batched_sensing"): {
-        "src": "d5e46f3bca4ba99c",
-        "fetch_kib": 3559.375, "write_kib": 64048457.5625,
-        "bytes": int(round((3559.375 * 2.000 + 64048457.5625 * 1.000) * 1024)),
+        "src": "8c478ecc0eeece22",
+        "fetch_kib": 3614.8125, "write_kib": 64054387.25,
+        "bytes": int(round((3614.8125 * 2.000 + 64054387.25 * 1.000) * 1024)),
     },
 }
 
