@@ -70,6 +70,31 @@ def test_elementwise_T_equals_factor_product(oracle):
         assert np.max(np.abs(T - _factor_product(th))) < 2e-15
 
 
+def test_transverse_angle_enters_only_through_jz_phases(oracle):
+    """The transverse direction phi enters the split factor only through
+    P = exp(-i phi J_z) = diag(e^{-i phi}, 1, e^{i phi}): rotating about z
+    carries J_x to J_phi and commutes with D, so T(theta) = P T0 P^H with T0
+    the factor at phi = 0, which is complex symmetric (J_x real symmetric, D
+    diagonal).  Squarings keep both properties.  Fails on a wrong sign or
+    power of e^{i phi} in any entry, or a transposed off-diagonal pair."""
+    m = np.array([1.0, 0.0, -1.0])
+    for th in _rand_theta(1.5, 60, 3):
+        rho = math.hypot(th[0], th[1])
+        phi = math.atan2(th[1], th[0])
+        th0 = np.array([rho, 0.0, th[2], th[3]])
+        P = np.diag(np.exp(-1j * phi * m))
+        for tau in (0, 1, 5, 28):
+            T0 = oracle.exp_one(th0, tau)
+            T = oracle.exp_one(th, tau)
+            assert np.max(np.abs(T0 - T0.T)) < 1e-14
+            assert np.max(np.abs(T - P @ T0 @ P.conj().T)) < 1e-14
+        a0 = oracle.lie_trotter_residual(th0, 28)
+        a = oracle.lie_trotter_residual(th, 28)
+        scale = np.max(np.abs(a0))
+        assert np.max(np.abs(a0 - a0.T)) / scale < 1e-15
+        assert np.max(np.abs(a - P @ a0 @ P.conj().T)) / scale < 1e-14
+
+
 def test_printed_T_entries_are_misprinted():
     """Documents the reading of the two garbled entries: with q != 0 the
     printed T_13 = -(sin(Phi/2) e^{iq/6} e^{-i phi})^2 and
