@@ -7,13 +7,17 @@
 
 namespace mss {
 
-// Product of the lane's (up to) E consecutive matrices, later on the left.
+// Product of the lane's (up to) E consecutive matrices, later on the left
+// (the identity for a lane past the end).  The first matrix is loaded as
+// the start value: multiplying it into the identity would give the same
+// entries.
 template <int N, int E>
 __device__ __forceinline__ void lane_product(const double* __restrict__ M, int64_t n, int64_t base,
                                              Mat<N>& Q) {
-  set_identity<N>(Q);
+  if (base < n) load_mat<N>(M + (size_t)base * 2 * N * N, Q);
+  else set_identity<N>(Q);
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
+  for (int e = 1; e < E; ++e) {
     const int64_t idx = base + e;
     if (idx < n) {
       Mat<N> X;
