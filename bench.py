@@ -5,8 +5,11 @@ Default workload: 4096 spin-1 sensing simulations of uneven length (10-100
 ms at 5e-7 s output steps, 10 CF4 steps per interval, tau = 28, rotating
 frame) run as one batch: the persistent integrator (interval operators from
 CF4 fine steps) followed by the segmented scan (states psi_k), both through
-the C ABI.  One step = one pass over the whole batch.  Inputs and outputs
-stay resident in HBM; the timed region starts after they are allocated.
+the C ABI.  The simulations share one field program (their parameters
+differ), which the plan compiles into the integrator at creation
+(mss_sampler_create_for_terms; the interpreter's time is reported beside it).
+One step = one pass over the whole batch.  Inputs and outputs stay resident
+in HBM; the timed region starts after they are allocated.
 
 Also measured in the same run: the plain path (one simulation per launch
 sequence) on the single spin-1 sensing simulation, and the batch replayed as
@@ -34,7 +37,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # the hash of the kernel sources it was taken with: reported only while the
 # sources are unchanged.
 MEASURED_TRAFFIC = {
-    ("batch_integrate_kernel", "batched_sensing"): {
+    ("mss_user_work_integrate", "batched_sensing"): {
         "src": "8c478ecc0eeece22",
         "fetch_kib": 3614.8125, "write_kib": 64054387.25,
         "bytes": int(round((3614.8125 * 2.000 + 64054387.25 * 1.000) * 1024)),
@@ -42,9 +45,12 @@ MEASURED_TRAFFIC = {
 }
 
 
-# sources that define the batched integrator (work_integrate_kernel)
+# sources that define the batched integrator: the field program compiled into
+# the persistent work-queue kernel at run time (mss_user_work_integrate: the
+# generated field function, the device headers it is compiled with, the
+# compile options and the launch)
 INTEGRATOR_SOURCES = ("mss_device.h", "mss_internal.h", "mss_work.h", "mss_work_device.h",
-                      "mss_work.hip")
+                      "mss_work.hip", "mss_user_kernels.h", "mss_sampler.hip")
 
 
 def kernel_source_hash() -> str:
@@ -84,11 +90,16 @@ def cpu_baseline(problems, seconds: float) -> dict:
                       f"{dt:.1f} s, {threads} OpenMP threads over intervals)"}
 
 
-def bench_plain(prob, steps: int, warmup: int) -> dict:
+def bench_plain(prob, steps: int, warmup: int, specialise: bool = True) -> dict:
+    """One simulation per launch sequence: the integrator (the field program
+    compiled into it, unless specialise is off) and the scan; the
+    interpreter's integrator is timed too."""
     import torch
     from paper_2204_05586_amd import native
     K, N = prob.n_samples, prob.dim
     params = native.device_params(prob)
+    sampler = native.Sampler.for_terms(prob.terms) if specialise else None
+    bare = prob.replace(terms=[])
     psi0 = native.device_state(prob.psi0)
     U = torch.empty((K, N, N), dtype=torch.complex128, device="cuda")
     psi = torch.empty((K, N), dtype=torch.complex128, device="cuda")
@@ -97,10 +108,16 @@ def bench_plain(prob, steps: int, warmup: int) -> dict:
     launch = native.plan_launch(prob)  # reported; the launch itself is the library's default
     stream = torch.cuda.current_stream()
 
+    def integrate(interpret=False):
+        if sampler is None or interpret:
+            native.integrate(prob, params, U, stream=stream)
+        else:
+            sampler.integrate(bare, params, U, stream=stream)
+
     def step(ev=None):
         if ev:
             ev[0].record(stream)
-        native.integrate(prob, params, U, stream=stream)
+        integrate()
         if ev:
             ev[1].record(stream)
         native.propagate(prob.spin_twice, U, psi0, psi, fin, ws, stream=stream)
@@ -124,19 +141,37 @@ def bench_plain(prob, steps: int, warmup: int) -> dict:
     wall = time.perf_counter() - t0
     integ = [e[0].elapsed_time(e[1]) for e in evs]
     prop = [e[1].elapsed_time(e[2]) for e in evs]
+    interp = []
+    for _ in range(max(steps, 1)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        integrate(interpret=True)
+        e1.record(stream)
+        interp.append((e0, e1))
+    torch.cuda.synchronize()
+    if sampler is not None:
+        sampler.close()
     return {"workload": prob.name, "fine_steps": prob.fine_steps,
             "value": prob.fine_steps * steps / wall, "ms_per_step": wall / steps * 1e3,
             "integrate_ms": statistics.mean(integ), "propagate_ms": statistics.mean(prop),
+            "integrate_ms_interpreter": statistics.mean(a.elapsed_time(b) for a, b in interp),
+            "field": "compiled in" if sampler is not None else "interpreted",
             "launch": {"slices": launch[0], "block": launch[1]}, "tau": prob.n_squares}
 
 
-def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool) -> dict:
+def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool,
+                  specialise: bool = True) -> dict:
+    """The batch plan (the shared field program compiled into the persistent
+    integrator, unless specialise is off); the interpreter's integrator is
+    timed on the same buffers too."""
     import torch
     from paper_2204_05586_amd import autotune, native
     t0 = time.perf_counter()
-    opts = autotune.tune(problems, cache_path=None) if tune else {}
+    opts = autotune.tune(problems, cache_path=None, specialize=specialise) if tune else {}
     tune_s = time.perf_counter() - t0
-    plan = native.BatchPlan(problems, **opts)
+    t0 = time.perf_counter()
+    plan = native.BatchPlan(problems, specialize=specialise, **opts)
+    compile_s = time.perf_counter() - t0
     bufs = plan.allocate(store_u=False)
     stream = torch.cuda.current_stream()
     fine = sum(p.fine_steps for p in problems)
@@ -163,12 +198,25 @@ def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool
     integ = [e[0].elapsed_time(e[1]) for e in evs]
     prop = [e[1].elapsed_time(e[2]) for e in evs]
     info = plan.info()
+    specialized = plan.specialized
     plan.close()
+    iplan = native.BatchPlan(problems, **opts)
+    interp = []
+    for _ in range(2):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        iplan.integrate(bufs, stream=stream)
+        e1.record(stream)
+        interp.append((e0, e1))
+    torch.cuda.synchronize()
+    iplan.close()
     out = {"value": fine * steps / wall, "ms_per_step": wall / steps * 1e3,
            "integrate_ms": statistics.mean(integ), "propagate_ms": statistics.mean(prop),
+           "integrate_ms_interpreter": statistics.mean(a.elapsed_time(b) for a, b in interp),
+           "specialized": specialized, "compile_s": compile_s,
            "fine_steps": fine, "info": info, "options": opts, "tune_s": tune_s}
     if graph_reps > 0:
-        gplan = native.BatchPlan(problems, use_graph=True, **opts)
+        gplan = native.BatchPlan(problems, use_graph=True, specialize=specialise, **opts)
         gplan.run(bufs, stream=stream)  # capture + first replay
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -295,6 +343,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="planner defaults, no autotuning")
+    ap.add_argument("--interpret", action="store_true",
+                    help="interpret the field program instead of compiling it into the integrator")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
                     help="target CPU seconds of the oracle sample (0: skip)")
     ap.add_argument("--serve-rates", default="10,100,1000",
@@ -322,21 +372,26 @@ def main():
     if args.workload == "batched_sensing":
         problems = W.batched_sensing(seed=2, n_sims=args.n_sims)
         tau = problems[0].n_squares
-        res = bench_batched(problems, args.steps, args.warmup, args.graph_reps, not args.no_tune)
-        kernel = "batch_integrate_kernel"
-        plain = (bench_plain(W.spin_one_sensing(), args.plain_steps, 3)
+        res = bench_batched(problems, args.steps, args.warmup, args.graph_reps, not args.no_tune,
+                            not args.interpret)
+        kernel = "mss_user_work_integrate" if res["specialized"] else "work_integrate_kernel"
+        plain = (bench_plain(W.spin_one_sensing(), args.plain_steps, 3, not args.interpret)
                  if args.plain_steps > 0 else None)
         value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
             res["fine_steps"]
         config = {"workload": f"batched_sensing: {len(problems)} spin-1 simulations, seed 2, "
                               f"durations U(10,100) ms, dt_out 5e-7 s",
-                  "mode": "batched (persistent integrator + segmented scan, eager launches)",
+                  "mode": ("batched (field program compiled into the persistent integrator"
+                           if res["specialized"] else "batched (field program interpreted by the "
+                           "persistent integrator") + " + segmented scan, eager launches)",
+                  "compile_s": round(res["compile_s"], 2),
                   "n_sims": len(problems), "total_intervals": res["info"]["total_samples"],
                   "n_fine": 10, "fine_steps": fine, "n_squares": tau, "rotating_frame": True,
                   "work_items": res["info"]["n_items"], "grid_blocks": res["info"]["grid_blocks"],
                   "scan_levels": res["info"]["scan_levels"], "autotuned": res["options"],
                   "autotune_s": round(res["tune_s"], 2)}
         extra = {"integrate_ms_mean": round(integ_ms, 3),
+                 "integrate_ms_interpreter": round(res["integrate_ms_interpreter"], 3),
                  "propagate_ms_mean": round(res["propagate_ms"], 3),
                  "graph_ms_per_step": round(res.get("graph_ms_per_step", 0.0), 3) or None,
                  "plain": ({k: (round(v, 4) if isinstance(v, float) else v)
@@ -346,15 +401,19 @@ def main():
     else:
         prob = W.spin_one_sensing() if args.workload == "spin_one_sensing" else W.spin_half_rabi()
         tau = prob.n_squares
-        res = bench_plain(prob, args.steps, args.warmup)
-        kernel = "integrate_kernel<3>" if prob.spin_twice == 2 else "integrate_kernel<2>"
+        res = bench_plain(prob, args.steps, args.warmup, not args.interpret)
+        n = prob.spin_twice + 1
+        kernel = (f"mss_user_integrate_{n}" if res["field"] == "compiled in"
+                  else f"integrate_kernel<{n}>")
         value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
             res["fine_steps"]
-        config = {"workload": prob.name, "mode": "plain (one simulation per launch sequence)",
+        config = {"workload": prob.name,
+                  "mode": f"plain (one simulation per launch sequence, field program {res['field']})",
                   "n_samples": prob.n_samples, "n_fine": prob.n_fine, "fine_steps": fine,
                   "n_squares": tau, "rotating_frame": prob.rotating_frame,
                   "launch": res["launch"]}
         extra = {"integrate_ms_mean": round(integ_ms, 4),
+                 "integrate_ms_interpreter": round(res["integrate_ms_interpreter"], 4),
                  "propagate_ms_mean": round(res["propagate_ms"], 4)}
         base_problems = [prob]
 

@@ -216,6 +216,30 @@ typedef struct mss_sampler_s* mss_sampler;
 mss_status mss_sampler_create(const char* source, const char* const* options, int32_t n_options,
                               mss_sampler* out);
 
+/* Specialised field program: a sampler whose mss_user_field is generated
+ * from a term list (the format of mss_problem.terms) and compiled as by
+ * mss_sampler_create.  The generated function performs the field-program
+ * interpreter's operations for these terms in the same order, so the
+ * operators it gives are bit for bit those of the interpreter on the same
+ * terms; the field is compiled into the integrator instead of interpreted
+ * per node (the counterpart of the paper's field function compiled into its
+ * integrator, Sec. "Compilation of integrator").  Problems run with it carry
+ * no terms (n_terms = 0) and at least mss_sampler_min_params(s) parameters:
+ * the terms' slots index that vector.  A term on the quadrupole component
+ * makes the sampler spin-1 only.  terms (host, n_terms in [0, MSS_MAX_TERMS])
+ * are read during the call only; the checks are those of a problem's terms.
+ * Errors as mss_sampler_create, plus MSS_E_INVALID for invalid terms. */
+mss_status mss_sampler_create_for_terms(const mss_term* terms, int32_t n_terms,
+                                        mss_sampler* out);
+
+/* Parameters a problem run with the sampler must carry: one past the
+ * highest slot its terms read (mss_sampler_create_for_terms), 0 for a
+ * sampler compiled from source (whose reads the caller keeps within
+ * n_params).  Problems with fewer are rejected with MSS_E_INVALID by
+ * mss_sampler_integrate, mss_sampler_solve and
+ * mss_batch_plan_create_sampled. */
+int32_t mss_sampler_min_params(mss_sampler s);
+
 /* Compiler log of a successful compile (warnings; "" if none).  Owned by
  * the sampler, valid until mss_sampler_destroy. */
 const char* mss_sampler_log(mss_sampler s);

@@ -31,6 +31,16 @@ def _arch() -> str:
     return f"{getattr(p, 'gcnArchName', p.name)}:{p.multi_processor_count}cu"
 
 
+def _sampler_id(sampler) -> Optional[str]:
+    """Cache identity of a sampler: a hash of its source, or of the term
+    list it was compiled from."""
+    if sampler is None:
+        return None
+    if sampler.source is not None:
+        return hashlib.sha256(sampler.source.encode()).hexdigest()[:16]
+    return "terms:" + hashlib.sha256(repr(native._terms_key(sampler.terms)).encode()).hexdigest()[:16]
+
+
 def shape_key(problems, sampler=None) -> str:
     spins = sorted({p.spin_twice for p in problems})
     taus = sorted({p.n_squares for p in problems if p.spin_twice == 2})
@@ -39,8 +49,7 @@ def shape_key(problems, sampler=None) -> str:
     total = sum(p.n_samples for p in problems)
     return json.dumps({"arch": _arch(), "spins": spins, "taus": taus, "fines": fines,
                        "frames": frames, "intervals_log2": int(round(math.log2(max(total, 1)))),
-                       "sampler": (hashlib.sha256(sampler.source.encode()).hexdigest()[:16]
-                                   if sampler is not None else None)},
+                       "sampler": _sampler_id(sampler)},
                       sort_keys=True)
 
 
@@ -73,10 +82,20 @@ def _time(plan: "native.BatchPlan", bufs: dict, what: str, reps: int) -> float:
 
 def tune(problems, cache_path: Optional[str] = DEFAULT_CACHE, reps: int = 3,
          target_fine_steps: float = 2e8, verbose: bool = False,
-         sampler: "Optional[native.Sampler]" = None) -> Dict[str, int]:
+         sampler: "Optional[native.Sampler]" = None,
+         specialize: bool = False) -> Dict[str, int]:
     """Options for BatchPlan(problems, **options), tuned (or read from the cache).
     With a sampler the trials run its integrator and the cache key includes
-    a hash of its source."""
+    a hash of its source.  specialize: tune the plan BatchPlan(problems,
+    specialize=True) makes (the shared field program compiled into its own
+    integrator), when the problems share one term list."""
+    if specialize and sampler is None:
+        sp = native.specialise(problems)
+        if sp is not None:
+            try:
+                return tune(sp[1], cache_path, reps, target_fine_steps, verbose, sampler=sp[0])
+            finally:
+                sp[0].close()
     key = shape_key(problems, sampler)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -130,6 +149,8 @@ def tune(problems, cache_path: Optional[str] = DEFAULT_CACHE, reps: int = 3,
     return best
 
 
-def tuned_plan(problems, use_graph: bool = False, sampler=None, **kw) -> "native.BatchPlan":
-    opts = tune(problems, sampler=sampler, **kw)
-    return native.BatchPlan(problems, use_graph=use_graph, sampler=sampler, **opts)
+def tuned_plan(problems, use_graph: bool = False, sampler=None, specialize: bool = False,
+               **kw) -> "native.BatchPlan":
+    opts = tune(problems, sampler=sampler, specialize=specialize, **kw)
+    return native.BatchPlan(problems, use_graph=use_graph, sampler=sampler,
+                            specialize=specialize, **opts)

@@ -135,6 +135,31 @@ ScanLevels plan_scan(int N, int64_t K) {
   return s;
 }
 
+mss_status validate_terms(int spin_twice, const mss_term* terms, int n_terms, int n_params) {
+  for (int i = 0; i < n_terms; ++i) {
+    const mss_term& t = terms[i];
+    if (t.kind < MSS_TERM_CONST || t.kind > MSS_TERM_PWC_SIN)
+      return api_fail(MSS_E_INVALID, "term %d: unknown kind %d", i, t.kind);
+    if (t.comp < 0 || t.comp > 3) return api_fail(MSS_E_INVALID, "term %d: comp must be 0..3", i);
+    if (t.comp == MSS_Q && spin_twice != 2)
+      return api_fail(MSS_E_INVALID, "term %d: the quadrupole component needs spin-1", i);
+    if (!finite(t.a) || !finite(t.f) || !finite(t.phi))
+      return api_fail(MSS_E_INVALID, "term %d: a, f, phi must be finite", i);
+    if (isnan(t.t_on) || isnan(t.t_off)) return api_fail(MSS_E_INVALID, "term %d: NaN window", i);
+    if (!slot_ok(t.a_slot, 1, n_params) || !slot_ok(t.f_slot, 1, n_params) ||
+        !slot_ok(t.phi_slot, 1, n_params))
+      return api_fail(MSS_E_INVALID, "term %d: parameter slot beyond n_params = %d", i, n_params);
+    if (t.kind >= MSS_TERM_PWC) {
+      if (t.n_seg < 1) return api_fail(MSS_E_INVALID, "term %d: n_seg must be >= 1", i);
+      if (!finite(t.seg_t0) || !finite(t.seg_len) || !(t.seg_len > 0.0))
+        return api_fail(MSS_E_INVALID, "term %d: seg_t0 finite and seg_len > 0 required", i);
+      if (!slot_ok(t.seg_a_slot, t.n_seg, n_params) || !slot_ok(t.seg_phi_slot, t.n_seg, n_params))
+        return api_fail(MSS_E_INVALID, "term %d: segment slots beyond n_params = %d", i, n_params);
+    }
+  }
+  return MSS_OK;
+}
+
 mss_status validate_problem(const mss_problem* p) {
   if (!p) return api_fail(MSS_E_INVALID, "problem is NULL");
   if (p->spin_twice != 1 && p->spin_twice != 2)
@@ -161,29 +186,7 @@ mss_status validate_problem(const mss_problem* p) {
     return api_fail(MSS_E_INVALID, "rotating_frame must be 0 or 1");
   if (p->method < MSS_CF4 || p->method > MSS_HEUN)
     return api_fail(MSS_E_INVALID, "unknown method %d", p->method);
-  for (int i = 0; i < p->n_terms; ++i) {
-    const mss_term& t = p->terms[i];
-    if (t.kind < MSS_TERM_CONST || t.kind > MSS_TERM_PWC_SIN)
-      return api_fail(MSS_E_INVALID, "term %d: unknown kind %d", i, t.kind);
-    if (t.comp < 0 || t.comp > 3) return api_fail(MSS_E_INVALID, "term %d: comp must be 0..3", i);
-    if (t.comp == MSS_Q && p->spin_twice != 2)
-      return api_fail(MSS_E_INVALID, "term %d: the quadrupole component needs spin-1", i);
-    if (!finite(t.a) || !finite(t.f) || !finite(t.phi))
-      return api_fail(MSS_E_INVALID, "term %d: a, f, phi must be finite", i);
-    if (isnan(t.t_on) || isnan(t.t_off)) return api_fail(MSS_E_INVALID, "term %d: NaN window", i);
-    if (!slot_ok(t.a_slot, 1, p->n_params) || !slot_ok(t.f_slot, 1, p->n_params) ||
-        !slot_ok(t.phi_slot, 1, p->n_params))
-      return api_fail(MSS_E_INVALID, "term %d: parameter slot beyond n_params = %d", i, p->n_params);
-    if (t.kind >= MSS_TERM_PWC) {
-      if (t.n_seg < 1) return api_fail(MSS_E_INVALID, "term %d: n_seg must be >= 1", i);
-      if (!finite(t.seg_t0) || !finite(t.seg_len) || !(t.seg_len > 0.0))
-        return api_fail(MSS_E_INVALID, "term %d: seg_t0 finite and seg_len > 0 required", i);
-      if (!slot_ok(t.seg_a_slot, t.n_seg, p->n_params) ||
-          !slot_ok(t.seg_phi_slot, t.n_seg, p->n_params))
-        return api_fail(MSS_E_INVALID, "term %d: segment slots beyond n_params = %d", i, p->n_params);
-    }
-  }
-  return MSS_OK;
+  return validate_terms(p->spin_twice, p->terms, p->n_terms, p->n_params);
 }
 
 }  // namespace
@@ -193,6 +196,9 @@ int api_device_cu_count() { return device_cu_count(); }
 int api_plan_slices(int64_t K, int32_t L, int cu) { return plan_slices(K, L, cu); }
 int api_ilog2(int x) { return ilog2(x); }
 mss_status api_validate_problem(const mss_problem* p) { return validate_problem(p); }
+mss_status api_validate_terms(int spin_twice, const mss_term* terms, int n_terms, int n_params) {
+  return validate_terms(spin_twice, terms, n_terms, n_params);
+}
 }  // namespace mss
 
 namespace {

@@ -229,9 +229,12 @@ mss_status mss_batch_plan_create_sampled(int32_t n, const mss_problem* problems,
   if (out) *out = nullptr;
   if (!sampler) return api_fail(MSS_E_INVALID, "sampler is NULL");
   if (n >= 1 && problems)
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
       if (problems[i].n_terms != 0)
         return api_fail(MSS_E_INVALID, "simulation %d: a sampler problem carries no terms", i);
+      const mss_status st = api_sampler_check_problem(sampler, &problems[i]);
+      if (st != MSS_OK) return st;
+    }
   return create_plan(n, problems, param_off, options, sampler, out);
 }
 

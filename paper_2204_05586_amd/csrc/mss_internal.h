@@ -26,6 +26,11 @@ mss_status api_ok();
 mss_status api_hip_fail(hipError_t e, const char* what);
 std::string api_last_error_copy();
 mss_status api_validate_problem(const mss_problem* p);
+// the term checks of api_validate_problem for a term list on its own
+mss_status api_validate_terms(int spin_twice, const mss_term* terms, int n_terms, int n_params);
+// a problem run with a sampler: its parameter vector covers what the
+// sampler reads, and its spin suits the sampler's components
+mss_status api_sampler_check_problem(mss_sampler s, const mss_problem* p);
 int api_device_cu_count();
 int api_plan_slices(int64_t K, int32_t L, int cu);
 int api_ilog2(int x);

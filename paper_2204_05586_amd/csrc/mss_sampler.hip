@@ -4,8 +4,11 @@
 // integrator launches.  The device headers are embedded by the build
 // (mss_rtc_sources.inc) so the library needs no source tree at run time.
 #include <hip/hiprtc.h>
+#include <math.h>
+#include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -24,6 +27,8 @@ struct mss_sampler_s {
   };
   std::vector<char> code;
   std::string log;
+  int32_t min_params = 0;      // parameters a problem must carry (terms' slots)
+  bool spin_one_only = false;  // a quadrupole term: spin-1 problems only
   std::mutex mu;
   std::map<int, Module> loaded;  // device ordinal -> module (entries never erased before destroy)
 };
@@ -84,9 +89,79 @@ mss_status load_on_current(mss_sampler s, const mss_sampler_s::Module** out) {
   return MSS_OK;
 }
 
+// Exact decimal-free spelling of a double for generated source.
+std::string hex_literal(double v) {
+  char b[64];
+  snprintf(b, sizeof b, "%a", v);
+  return std::string("(") + b + ")";
+}
+
+std::string slot_or_literal(int32_t slot, double v) {
+  return slot >= 0 ? "p[" + std::to_string(slot) + "]" : hex_literal(v);
+}
+
+// HIP source of mss_user_field for a term list: the field-program
+// interpreter's operations for these terms, in the same order and with the
+// same contraction (none), so that the compiled integrator reproduces the
+// interpreter's operators bit for bit.  Window bounds that are infinite are
+// left out (every finite t passes them); a term whose window holds no
+// finite time is left out altogether.
+std::string specialised_source(const mss_term* terms, int n) {
+  std::string s;
+  s += "__device__ void mss_user_field(double t, const double* p, double* f) {\n";
+  s += "#pragma clang fp contract(off)\n";
+  s += "  double fc[4] = {0.0, 0.0, 0.0, 0.0};\n";
+  for (int i = 0; i < n; ++i) {
+    const mss_term& tm = terms[i];
+    if (tm.t_on == INFINITY || tm.t_off == -INFINITY || !(tm.t_on < tm.t_off)) continue;
+    std::string cond;
+    if (tm.t_on != -INFINITY) cond = hex_literal(tm.t_on) + " < t";
+    if (tm.t_off != INFINITY) cond += (cond.empty() ? "" : " && ") + std::string("t < ") + hex_literal(tm.t_off);
+    s += "  // term " + std::to_string(i) + "\n";
+    s += cond.empty() ? "  {\n" : "  if (" + cond + ") {\n";
+    s += "    double amp = " + slot_or_literal(tm.a_slot, tm.a) + ";\n";
+    s += "    double ph = " + slot_or_literal(tm.phi_slot, tm.phi) + ";\n";
+    if (tm.kind >= MSS_TERM_PWC) {
+      s += "    const double x = (t - " + hex_literal(tm.seg_t0) + ") / " + hex_literal(tm.seg_len) +
+           ";\n";
+      s += "    const double fl = floor(x);\n";
+      s += "    const int s = fl < 0.0 ? 0 : (fl > (double)(" + std::to_string(tm.n_seg - 1) +
+           ") ? " + std::to_string(tm.n_seg - 1) + " : (int)fl);\n";
+      if (tm.seg_a_slot >= 0) s += "    amp = p[" + std::to_string(tm.seg_a_slot) + " + s];\n";
+      if (tm.seg_phi_slot >= 0) s += "    ph = p[" + std::to_string(tm.seg_phi_slot) + " + s];\n";
+    }
+    if (tm.kind == MSS_TERM_CONST || tm.kind == MSS_TERM_PWC) {
+      s += "    const double v = amp;\n";
+    } else {
+      const bool is_cos = tm.kind == MSS_TERM_COS || tm.kind == MSS_TERM_PWC_COS;
+      s += "    const double fr = " + slot_or_literal(tm.f_slot, tm.f) + ";\n";
+      s += "    const double ft = fr * t;\n";
+      s += "    const double xr = mss::kTwoPi * ft;\n";
+      s += "    const double arg = xr + ph;\n";
+      s += "    double sn, cs;\n";
+      s += "    mss::sincos_cw(arg, &sn, &cs);\n";
+      s += std::string("    const double v = amp * ") + (is_cos ? "cs" : "sn") + ";\n";
+    }
+    s += "    fc[" + std::to_string(tm.comp) + "] = fc[" + std::to_string(tm.comp) + "] + v;\n";
+    s += "  }\n";
+  }
+  s += "  f[0] = fc[0];\n  f[1] = fc[1];\n  f[2] = fc[2];\n  f[3] = fc[3];\n}\n";
+  return s;
+}
+
 }  // namespace
 
 namespace mss {
+mss_status api_sampler_check_problem(mss_sampler s, const mss_problem* p) {
+  if (p->n_params < s->min_params)
+    return api_fail(MSS_E_INVALID,
+                    "the sampler's terms read %d parameters, the problem has n_params = %d",
+                    s->min_params, p->n_params);
+  if (s->spin_one_only && p->spin_twice != 2)
+    return api_fail(MSS_E_INVALID, "the sampler's terms have a quadrupole component: spin-1 only");
+  return MSS_OK;
+}
+
 mss_status api_sampler_work_function(mss_sampler s, hipFunction_t* fn) {
   const mss_sampler_s::Module* m = nullptr;
   mss_status st = load_on_current(s, &m);
@@ -155,6 +230,37 @@ mss_status mss_sampler_create(const char* source, const char* const* options, in
   return api_ok();
 }
 
+mss_status mss_sampler_create_for_terms(const mss_term* terms, int32_t n_terms,
+                                        mss_sampler* out) {
+  if (!out) return api_fail(MSS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n_terms < 0 || n_terms > MSS_MAX_TERMS)
+    return api_fail(MSS_E_INVALID, "n_terms must be in [0, %d], got %d", MSS_MAX_TERMS, n_terms);
+  if (n_terms > 0 && !terms) return api_fail(MSS_E_INVALID, "terms is NULL");
+  int32_t need = 0;
+  bool quad = false;
+  for (int i = 0; i < n_terms; ++i) {
+    const mss_term& t = terms[i];
+    const int32_t one[3] = {t.a_slot, t.f_slot, t.phi_slot};
+    for (int32_t v : one)
+      if (v >= 0) need = std::max(need, v + 1);
+    if (t.kind >= MSS_TERM_PWC && t.n_seg >= 1) {
+      if (t.seg_a_slot >= 0) need = std::max(need, t.seg_a_slot + t.n_seg);
+      if (t.seg_phi_slot >= 0) need = std::max(need, t.seg_phi_slot + t.n_seg);
+    }
+    quad = quad || t.comp == MSS_Q;
+  }
+  mss_status st = api_validate_terms(2, terms, n_terms, need);
+  if (st != MSS_OK) return st;
+  const std::string src = specialised_source(terms, n_terms);
+  if ((st = mss_sampler_create(src.c_str(), nullptr, 0, out)) != MSS_OK) return st;
+  (*out)->min_params = need;
+  (*out)->spin_one_only = quad;
+  return api_ok();
+}
+
+int32_t mss_sampler_min_params(mss_sampler s) { return s ? s->min_params : 0; }
+
 const char* mss_sampler_log(mss_sampler s) { return s ? s->log.c_str() : ""; }
 
 mss_status mss_sampler_integrate(mss_sampler s, const mss_problem* p, const double* params,
@@ -166,6 +272,7 @@ mss_status mss_sampler_integrate(mss_sampler s, const mss_problem* p, const doub
     return api_fail(MSS_E_INVALID, "a sampler problem carries no terms (n_terms = %d)", p->n_terms);
   if (!U) return api_fail(MSS_E_INVALID, "U is NULL");
   if (p->n_params > 0 && !params) return api_fail(MSS_E_INVALID, "params is NULL but n_params > 0");
+  if ((st = api_sampler_check_problem(s, p)) != MSS_OK) return st;
   int S, B;
   bool given = false;
   if ((st = api_resolve_launch(p, launch, &S, &B, &given)) != MSS_OK) return st;

@@ -33,6 +33,7 @@ EXPORTS = [
     "mss_adjoint_workspace_size", "mss_adjoint_param_count", "mss_adjoint_run",
     "mss_adjoint_plan_destroy", "mss_sampler_create", "mss_sampler_log", "mss_sampler_integrate",
     "mss_sampler_solve", "mss_sampler_destroy", "mss_batch_plan_create_sampled",
+    "mss_sampler_create_for_terms", "mss_sampler_min_params",
 ]
 
 MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
@@ -161,6 +162,9 @@ def lib() -> C.CDLL:
         L.mss_sampler_log.restype = C.c_char_p
         L.mss_sampler_integrate.argtypes = [vp, PP, vp, vp, vp, C.POINTER(Launch), vp]
         L.mss_sampler_solve.argtypes = [vp, PP, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_sampler_create_for_terms.argtypes = [C.POINTER(Term), C.c_int32, C.POINTER(vp)]
+        L.mss_sampler_min_params.argtypes = [vp]
+        L.mss_sampler_min_params.restype = C.c_int32
         L.mss_sampler_destroy.argtypes = [vp]
         L.mss_sampler_destroy.restype = None
         for name in ("mss_validate", "mss_plan_launch", "mss_workspace_size",
@@ -192,17 +196,33 @@ def version() -> str:
     return lib().mss_version().decode()
 
 
+def _term_array(terms):
+    """A ctypes mss_term array of a term list (at least one element)."""
+    terms = list(terms)
+    arr = (Term * max(1, len(terms)))()
+    for i, t in enumerate(terms):
+        arr[i] = Term(int(t.kind), int(t.comp), int(t.a_slot), int(t.f_slot),
+                      int(t.phi_slot), int(t.n_seg), int(t.seg_a_slot), int(t.seg_phi_slot),
+                      float(t.a), float(t.f), float(t.phi), float(t.t_on), float(t.t_off),
+                      float(t.seg_t0), float(t.seg_len))
+    return arr
+
+
+def _terms_key(terms) -> tuple:
+    """Exact identity of a term list (every field, floats bit for bit)."""
+    return tuple((int(t.kind), int(t.comp), int(t.a_slot), int(t.f_slot), int(t.phi_slot),
+                  int(t.n_seg), int(t.seg_a_slot), int(t.seg_phi_slot),
+                  float(t.a).hex(), float(t.f).hex(), float(t.phi).hex(), float(t.t_on).hex(),
+                  float(t.t_off).hex(), float(t.seg_t0).hex(), float(t.seg_len).hex())
+                 for t in terms)
+
+
 class PackedProblem:
     """A ctypes mss_problem with its term array kept alive."""
 
     def __init__(self, prob):
         terms = list(prob.terms)
-        arr = (Term * max(1, len(terms)))()
-        for i, t in enumerate(terms):
-            arr[i] = Term(int(t.kind), int(t.comp), int(t.a_slot), int(t.f_slot),
-                          int(t.phi_slot), int(t.n_seg), int(t.seg_a_slot), int(t.seg_phi_slot),
-                          float(t.a), float(t.f), float(t.phi), float(t.t_on), float(t.t_off),
-                          float(t.seg_t0), float(t.seg_len))
+        arr = _term_array(terms)
         self.terms = arr
         n_params = int(np.asarray(prob.params).size)
         self.c = Problem(int(prob.spin_twice), len(terms), arr, n_params, int(prob.n_fine),
@@ -341,6 +361,27 @@ class Sampler:
         check(lib().mss_sampler_create(source.encode(), arr, len(opts), C.byref(h)))
         self._h = h
         self.source = source
+        self.terms = None
+
+    @classmethod
+    def for_terms(cls, terms) -> "Sampler":
+        """The field program ``terms`` compiled into its own integrator
+        (mss_sampler_create_for_terms): the interpreter's arithmetic for
+        these terms, so the operators are bit for bit the interpreter's.
+        Problems run with it carry no terms and at least ``min_params``
+        parameters."""
+        terms = list(terms)
+        h = C.c_void_p()
+        check(lib().mss_sampler_create_for_terms(_term_array(terms), len(terms), C.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.source = None
+        self.terms = terms
+        return self
+
+    @property
+    def min_params(self) -> int:
+        return int(lib().mss_sampler_min_params(self._h))
 
     @property
     def log(self) -> str:
@@ -375,6 +416,19 @@ class Sampler:
 
 # ---- batches ---------------------------------------------------------------
 
+def specialise(problems) -> "Optional[tuple[Sampler, list]]":
+    """When every problem has the same term list, that field program
+    compiled into its own integrator and the problems without their terms
+    (what a sampler runs); None otherwise.  The caller owns the sampler."""
+    problems = list(problems)
+    if not problems:
+        return None
+    key = _terms_key(problems[0].terms)
+    if any(_terms_key(p.terms) != key for p in problems[1:]):
+        return None
+    return Sampler.for_terms(problems[0].terms), [p.replace(terms=[]) for p in problems]
+
+
 class BatchPlan:
     """A planned batch of simulations (mss_batch_plan_create).
 
@@ -382,11 +436,25 @@ class BatchPlan:
     psi0_off[i], its states at state_off[i] and its operators at op_off[i]
     (complex units).  Parameters are concatenated in simulation order.
     sampler: a ``Sampler`` giving every simulation's field (problems then
-    carry no terms); kept alive by the plan."""
+    carry no terms); kept alive by the plan.
+    specialize: when every problem has the same term list (parameters may
+    differ), compile that field program into its own integrator
+    (``Sampler.for_terms``, bit-for-bit the interpreter's operators) and run
+    the batch with it; otherwise the terms are interpreted.  The plan owns
+    that sampler; ``specialized`` tells which happened."""
 
     def __init__(self, problems, slices_spin_half=0, slices_spin_one=0, waves_per_simd=0,
-                 use_graph=False, scan_per_lane=0, sampler: "Optional[Sampler]" = None):
+                 use_graph=False, scan_per_lane=0, sampler: "Optional[Sampler]" = None,
+                 specialize: bool = False):
         self.problems = list(problems)
+        self._own_sampler = None
+        self.specialized = False
+        if specialize and sampler is None:
+            sp = specialise(self.problems)
+            if sp is not None:
+                sampler, self.problems = sp
+                self._own_sampler = sampler
+                self.specialized = True
         n = len(self.problems)
         self.packed = [PackedProblem(p) for p in self.problems]
         arr = (Problem * max(1, n))()
@@ -486,6 +554,9 @@ class BatchPlan:
         if getattr(self, "handle", None):
             lib().mss_batch_plan_destroy(self.handle)
             self.handle = None
+        if getattr(self, "_own_sampler", None) is not None:
+            self._own_sampler.close()
+            self._own_sampler = None
 
     def __del__(self):
         try:

@@ -124,6 +124,69 @@ def test_sampler_compile_errors_name_the_user_line():
         native.Sampler("int unrelated;")
 
 
+def _kinds_terms(quad):
+    T = W.Term
+    terms = [T(W.CONST, W.Z, a=1.0e3), T(W.COS, W.X, a=2.0e2, f=1.0e3, phi=0.3),
+             T(W.SIN, W.Y, a_slot=0, f_slot=1, phi_slot=2, t_on=1e-3, t_off=2e-3),
+             T(W.PWC, W.X, n_seg=4, seg_a_slot=3, seg_t0=0.0, seg_len=1e-3),
+             T(W.PWC_COS, W.X, f=5.0, n_seg=3, seg_a_slot=7, seg_phi_slot=10, seg_t0=0.0,
+               seg_len=1e-3, t_off=0.5),
+             T(W.PWC_SIN, W.Y, a=2.0, f=7.0, n_seg=2, seg_phi_slot=13, seg_t0=-1.0, seg_len=0.5,
+               t_on=-0.1),
+             T(W.COS, W.X, a=1.0, f=1.0, t_on=1.0, t_off=1.0)]
+    if quad:
+        terms.append(T(W.CONST, W.Q, a=-0.0))
+    return terms
+
+
+def test_sampler_for_terms_compiles_without_gpu():
+    """Every term kind compiles into a specialised sampler; it needs the
+    parameters up to the highest slot read (segment slots count n_seg)."""
+    for quad in (False, True):
+        s = native.Sampler.for_terms(_kinds_terms(quad))
+        assert s.min_params == 15 and s.terms is not None
+        s.close()
+    s = native.Sampler.for_terms([])
+    assert s.min_params == 0
+    s.close()
+    assert native.lib().mss_sampler_min_params(None) == 0
+
+
+def test_sampler_for_terms_rejects_invalid_terms():
+    T = W.Term
+    for bad, msg in [([T(W.PWC, W.X, n_seg=0, seg_t0=0.0, seg_len=1.0)], "n_seg"),
+                     ([T(7, W.X)], "unknown kind"),
+                     ([T(W.COS, W.X, a=float("nan"))], "finite"),
+                     ([T(W.CONST, W.X, t_on=float("nan"))], "NaN window"),
+                     ([T(W.PWC, W.X, n_seg=2, seg_t0=0.0, seg_len=0.0)], "seg_len")]:
+        with pytest.raises(native.MssError, match=msg):
+            native.Sampler.for_terms(bad)
+    h = C.c_void_p()
+    assert native.lib().mss_sampler_create_for_terms(None, 1, C.byref(h)) == native.MSS_E_INVALID
+    assert native.lib().mss_sampler_create_for_terms(None, 0, None) == native.MSS_E_INVALID
+
+
+def test_sampler_for_terms_checks_problems_before_launch():
+    """A problem run with a specialised sampler carries the parameters its
+    terms read, and spin-1 when they include a quadrupole term; the batch
+    plan checks every simulation the same way.  All rejected before any
+    device work."""
+    s = native.Sampler.for_terms(_kinds_terms(True))
+    L = native.lib()
+    dummy = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    short = W.Problem(2, [], 0.0, 1e-6, 10, 2, 28, True, params=np.zeros(14))
+    pk = native.PackedProblem(short)
+    assert L.mss_sampler_integrate(s._h, pk.ref, dummy, dummy, None, None, None) == native.MSS_E_INVALID
+    assert "15 parameters" in native.last_error()
+    half = W.Problem(1, [], 0.0, 1e-6, 10, 2, 28, True, params=np.zeros(15))
+    pk = native.PackedProblem(half)
+    assert L.mss_sampler_integrate(s._h, pk.ref, dummy, dummy, None, None, None) == native.MSS_E_INVALID
+    assert "spin-1 only" in native.last_error()
+    with pytest.raises(native.MssError, match="15 parameters"):
+        native.BatchPlan([short.replace(params=np.zeros(15)), short], sampler=s)
+    s.close()
+
+
 def test_sampler_integrate_validates_before_launch():
     from tests import user_fields as F
     s = native.Sampler(F.LZ_SOURCE)
