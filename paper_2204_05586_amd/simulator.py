@@ -5,10 +5,12 @@ different sweep parameters, returning ``Results`` (time, state, time
 evolution operators).
 
 The field is either a field program (a list of ``workloads.Term``,
-interpreted by the precompiled integrator) or, like the paper's user field
-function, code: HIP source defining ``mss_user_field(t, params, field)``,
-compiled at run time into its own integrator (``native.Sampler``).
-``params`` plays the role of sweep_parameters.
+interpreted by the precompiled integrator, or with ``specialize=True``
+compiled once into its own integrator at construction, as the paper compiles
+its field function) or, like the paper's user field function, code: HIP
+source defining ``mss_user_field(t, params, field)``, compiled at run time
+into its own integrator (``native.Sampler``).  ``params`` plays the role of
+sweep_parameters.
 """
 from __future__ import annotations
 
@@ -60,7 +62,9 @@ class Simulator:
 
     spin: 0.5 or 1.  terms: field program, or HIP source of a field function
     (str), or a compiled ``native.Sampler``; sampler_options: extra compiler
-    options for a source.  rotating_frame: per-interval
+    options for a source.  specialize: compile a field program into its own
+    integrator at construction (about a second; the operators are bit for bit
+    the interpreter's, and each evaluation is faster).  rotating_frame: per-interval
     rotating frame (paper default: on).  n_squares: Lie-Trotter squaring
     count tau for spin-1 (paper default 24).  method: "cf4" (default), or
     the Euler-family comparison samplings "midpoint" and "heun"."""
@@ -69,7 +73,7 @@ class Simulator:
 
     def __init__(self, terms, spin: float = 1, rotating_frame: bool = True,
                  n_squares: int = 24, method: str = "cf4", device: str = "cuda",
-                 sampler_options: Sequence[str] = ()):
+                 sampler_options: Sequence[str] = (), specialize: bool = False):
         if spin not in (0.5, 1, 1.0):
             raise ValueError("spin must be 0.5 or 1")
         if method not in self.METHODS:
@@ -83,6 +87,8 @@ class Simulator:
         elif isinstance(terms, native.Sampler):
             self.sampler, terms = terms, []
         self.terms: List[Term] = list(terms)
+        if specialize and self.sampler is None:
+            self.sampler = native.Sampler.for_terms(self.terms)
         self.rotating_frame = bool(rotating_frame)
         self.n_squares = int(n_squares)
         self.device = device
@@ -99,6 +105,8 @@ class Simulator:
                  stream=None) -> Results:
         prob = self.problem(t_start, t_end, dt_integration, dt_output, params, psi0)
         native.validate(prob)
+        if self.sampler is not None:
+            prob = prob.replace(terms=[])
         r = native.solve(prob, store_u=keep_operators, want_time=True, device=self.device,
                          stream=stream, sampler=self.sampler)
         return Results(r["time"], r["psi"], r["U"], r["psi_final"])

@@ -159,6 +159,22 @@ def test_simulator_front_end(dev, oracle):
     assert np.max(np.abs(res.time_evolution.cpu().numpy() - ref["U"])) <= TOL
 
 
+def test_simulator_specialised_field(dev, oracle):
+    """A Simulator that compiles its field program at construction gives the
+    interpreting Simulator's states (same lane plan) and the oracle's."""
+    from paper_2204_05586_amd import Simulator
+    args = ([0.6, 0.8j, 0], 0.0495, 0.0505, 5e-8, 5e-7)
+    a = Simulator(W.neural_pulse_terms(), spin=1, n_squares=28, specialize=True)
+    b = Simulator(W.neural_pulse_terms(), spin=1, n_squares=28)
+    ra, rb = a.evaluate(*args), b.evaluate(*args)
+    ref = oracle.solve(a.problem(0.0495, 0.0505, 5e-8, 5e-7, psi0=args[0]), want_U=True)
+    assert np.max(np.abs(ra.state.cpu().numpy() - ref["psi"])) <= TOL
+    assert np.max(np.abs(ra.time_evolution.cpu().numpy() - ref["U"])) <= TOL
+    print(f"[gpu] specialised vs interpreted simulator: "
+          f"{float((ra.state - rb.state).abs().max()):.3e}", flush=True)
+    a.sampler.close()
+
+
 def test_spin_projection(dev, oracle):
     """<J> of the GPU states vs the oracle's <J> of the oracle's states, and
     the projection kernel alone on identical inputs."""
