@@ -21,9 +21,22 @@
 //     T_13 carries exp(-i q/6) inside the square and T_22 = cos(Phi) exp(2iq/3)),
 //     built as the residual a = T - I with expm1-style diagonals, then tau
 //     residual squarings a <- (a + 2I) a, then I + a.
+//   * Spin-1 with the full su(3) basis (Sec. "Spin-one" extension to
+//     H = ... + w_u1 U_1 + w_u2 U_2 + w_v1 V_1 + w_v2 V_2): the paper takes
+//     U_1, U_2, V_1, V_2 from a reference it does not print, and includes a
+//     general exponentiator without describing it.  Readings here:
+//     U_1 = J_x^2 - J_y^2, U_2 = J_x J_y + J_y J_x (the Delta m = +-2
+//     quadrupoles) and V_1 = J_z J_x + J_x J_z, V_2 = J_y J_z + J_z J_y (the
+//     Delta m = +-1 quadrupoles); exp(-i G) by scaling and squaring: the
+//     residual of exp(-i G / n), n = 2^tau, as its Taylor polynomial of degree
+//     4, then the same tau residual squarings.  A spin-1 problem uses it when
+//     any of its terms is on U_1, U_2, V_1 or V_2.
 //   * Dynamic rotating frame (Sec. "Dynamically rotating frame"):
 //     omega_r = omega_z(t_k + Dt/2); within an interval the transverse field
 //     is rotated by exp(-i omega_r (t - t_k)) and omega_z -> omega_z - omega_r;
+//     the full-basis pairs (w_u1 + i w_u2) and (w_v1 + i w_v2) by
+//     exp(-2i omega_r (t - t_k)) and exp(-i omega_r (t - t_k)) (they carry
+//     Delta m = 2 and 1 under rotations about z);
 //     on exit U_k = R(-Dt) U_k^r = diag(exp(-i m omega_r Dt)) U_k^r
 //     (eq. exit_rotating_frame).
 //   * Discretisation (Sec. "Discretization and parallelization"): t_k =
@@ -79,6 +92,17 @@ struct OProblem {
 
 enum { K_CONST = 0, K_COS = 1, K_SIN = 2, K_PWC = 3, K_PWC_COS = 4, K_PWC_SIN = 5 };
 
+// field components: x, y, z, q, then the full-basis quadrupoles u1, u2, v1, v2
+constexpr int kComps = 8;
+
+// Does the problem need the full su(3) basis (a term on u1, u2, v1 or v2)?
+inline bool full_basis(const OProblem& p) {
+  if (p.spin_twice != 2 || p.field_fn) return false;
+  for (int i = 0; i < p.n_terms; ++i)
+    if (p.terms[i].comp >= 4) return true;
+  return false;
+}
+
 template <class R> using cx = std::complex<R>;
 
 using std::acos;
@@ -126,10 +150,11 @@ inline void call_field_fn(const OProblem& p, const double* params, double t, dou
 template <class R>
 void call_field_fn(const OProblem&, const R*, R, R*) {}
 
-// Field functions f_j(t) in Hz, j = x, y, z, q.  Terms are summed in list order.
+// Field functions f_j(t) in Hz, j = x, y, z, q, u1, u2, v1, v2.  Terms are
+// summed in list order.  A field function fills the first four.
 template <class R>
-void field(const OProblem& p, const R* params, R t, R out[4]) {
-  for (int j = 0; j < 4; ++j) out[j] = R(0);
+void field(const OProblem& p, const R* params, R t, R out[kComps]) {
+  for (int j = 0; j < kComps; ++j) out[j] = R(0);
   if (p.field_fn) {
     call_field_fn(p, params, t, out);
     return;
@@ -307,12 +332,89 @@ Mat<R, 3> exp_one(const R th[4], int tau) {
   return a;
 }
 
+// The eight spin-1 basis operators A_j, j = x, y, z, q, u1, u2, v1, v2, in
+// the basis |+1>, |0>, |-1>: J_x, J_y with 1/sqrt 2 couplings between
+// neighbouring levels, J_z = diag(1, 0, -1), Q = diag(1, -2, 1) / 3,
+// U_1 = J_x^2 - J_y^2, U_2 = J_x J_y + J_y J_x, V_1 = J_z J_x + J_x J_z,
+// V_2 = J_y J_z + J_z J_y (products formed here, not written out).
+template <class R>
+Mat<R, 3> basis_operator(int j) {
+  const R r = R(1) / sqrt(R(2));
+  Mat<R, 3> Jx, Jy, Jz;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Jx.m[a][b] = Jy.m[a][b] = Jz.m[a][b] = cx<R>(0, 0);
+  Jx.m[0][1] = Jx.m[1][0] = Jx.m[1][2] = Jx.m[2][1] = cx<R>(r, 0);
+  Jy.m[0][1] = Jy.m[1][2] = cx<R>(0, -r);
+  Jy.m[1][0] = Jy.m[2][1] = cx<R>(0, r);
+  Jz.m[0][0] = cx<R>(1, 0);
+  Jz.m[2][2] = cx<R>(-1, 0);
+  auto add = [](const Mat<R, 3>& A, const Mat<R, 3>& B, R sb) {
+    Mat<R, 3> C;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) C.m[a][b] = A.m[a][b] + sb * B.m[a][b];
+    return C;
+  };
+  switch (j) {
+    case 0: return Jx;
+    case 1: return Jy;
+    case 2: return Jz;
+    case 3: {
+      Mat<R, 3> Q = Mat<R, 3>::identity();
+      Q.m[0][0] = cx<R>(R(1) / R(3), 0);
+      Q.m[1][1] = cx<R>(R(-2) / R(3), 0);
+      Q.m[2][2] = cx<R>(R(1) / R(3), 0);
+      return Q;
+    }
+    case 4: return add(matmul(Jx, Jx), matmul(Jy, Jy), R(-1));
+    case 5: return add(matmul(Jx, Jy), matmul(Jy, Jx), R(1));
+    case 6: return add(matmul(Jz, Jx), matmul(Jx, Jz), R(1));
+    default: return add(matmul(Jy, Jz), matmul(Jz, Jy), R(1));
+  }
+}
+
+// Spin-1, full basis: exp(-i G), G = sum_j theta_j A_j, by scaling and
+// squaring.  X = -i G / n with n = 2^tau; the residual of exp(X) from its
+// degree-4 Taylor polynomial, a = X + X^2/2 + X^3/6 + X^4/24 (no identity
+// term, so nothing cancels), then tau residual squarings and I + a.
+template <class R>
+Mat<R, 3> exp_full(const R th[kComps], int tau) {
+  const R n = ldexp(R(1), tau);
+  Mat<R, 3> X;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) X.m[a][b] = cx<R>(0, 0);
+  for (int j = 0; j < kComps; ++j) {
+    const Mat<R, 3> A = basis_operator<R>(j);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) X.m[a][b] += cx<R>(th[j], 0) * A.m[a][b];
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) X.m[a][b] = cx<R>(0, -1) * X.m[a][b] / n;
+  Mat<R, 3> a = Mat<R, 3>::identity();  // Horner: I + X/4, I + X/3 (...), I + X/2 (...)
+  for (int k = 4; k >= 2; --k) {
+    Mat<R, 3> t = matmul(X, a);
+    a = Mat<R, 3>::identity();
+    for (int i = 0; i < 3; ++i)
+      for (int jj = 0; jj < 3; ++jj) a.m[i][jj] += t.m[i][jj] / R(k);
+  }
+  a = matmul(X, a);
+  for (int s = 0; s < tau; ++s) {
+    Mat<R, 3> b = a;
+    for (int i = 0; i < 3; ++i) b.m[i][i] += cx<R>(R(2), R(0));
+    a = matmul(b, a);
+  }
+  for (int i = 0; i < 3; ++i) a.m[i][i] += cx<R>(R(1), R(0));
+  return a;
+}
+
+// the exponential of one step's angles (full: the su(3) exponentiator)
 template <class R, int N> struct Exp;
 template <class R> struct Exp<R, 2> {
-  static Mat<R, 2> apply(const R th[4], int) { return exp_half(th); }
+  static Mat<R, 2> apply(const R th[kComps], int, bool) { return exp_half(th); }
 };
 template <class R> struct Exp<R, 3> {
-  static Mat<R, 3> apply(const R th[4], int tau) { return exp_one(th, tau); }
+  static Mat<R, 3> apply(const R th[kComps], int tau, bool full) {
+    return full ? exp_full(th, tau) : exp_one(th, tau);
+  }
 };
 
 // magnetic quantum numbers m = s, ..., -s of the basis states
@@ -331,10 +433,11 @@ Mat<R, N> interval_operator(const OProblem& p, const R* params, int64_t k) {
   const R tk = R(p.t_start) + R(k) * Dt;
   R wr = R(0);
   if (p.rotating_frame) {
-    R f[4];
+    R f[kComps];
     field<R>(p, params, tk + Dt / R(2), f);
     wr = two_pi<R>() * f[2];
   }
+  const bool full = full_basis(p);
   Mat<R, N> U = Mat<R, N>::identity();
   // sampling nodes (fractions of the fine step) and number of exponentials
   // per step: CF4 two Gauss nodes and two exponentials; the Euler-family
@@ -348,31 +451,40 @@ Mat<R, N> interval_operator(const OProblem& p, const R* params, int64_t k) {
     cnode[1] = R(1);
   }
   for (int l = 0; l < p.n_fine; ++l) {
-    R w[2][4];
+    R w[2][kComps];
     for (int i = 0; i < nn; ++i) {
       const R tau_i = (R(l) + cnode[i]) * dt;
-      R f[4];
+      R f[kComps];
       field<R>(p, params, tk + tau_i, f);
-      for (int j = 0; j < 4; ++j) w[i][j] = two_pi<R>() * f[j];
+      for (int j = 0; j < kComps; ++j) w[i][j] = two_pi<R>() * f[j];
       // rotating frame: transverse field rotated by exp(-i omega_r (t - t_k))
       cx<R> xy = cx<R>(w[i][0], w[i][1]) * expi(-(wr * tau_i));
       w[i][0] = xy.real();
       w[i][1] = xy.imag();
       w[i][2] = w[i][2] - wr;
+      if (full) {
+        // Delta m = 2 pair by exp(-2i omega_r (t - t_k)), Delta m = 1 pair by exp(-i ...)
+        cx<R> u = cx<R>(w[i][4], w[i][5]) * expi(-(R(2) * (wr * tau_i)));
+        cx<R> v = cx<R>(w[i][6], w[i][7]) * expi(-(wr * tau_i));
+        w[i][4] = u.real();
+        w[i][5] = u.imag();
+        w[i][6] = v.real();
+        w[i][7] = v.imag();
+      }
     }
-    R th1[4], th2[4];
+    R th1[kComps], th2[kComps];
     if (p.method == 0) {
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < kComps; ++j) {
         th1[j] = (wp * w[0][j] + wm * w[1][j]) * dt;
         th2[j] = (wm * w[0][j] + wp * w[1][j]) * dt;
       }
-      Mat<R, N> E1 = Exp<R, N>::apply(th1, p.n_squares);
-      Mat<R, N> E2 = Exp<R, N>::apply(th2, p.n_squares);
+      Mat<R, N> E1 = Exp<R, N>::apply(th1, p.n_squares, full);
+      Mat<R, N> E2 = Exp<R, N>::apply(th2, p.n_squares, full);
       U = matmul(E2, matmul(E1, U));
     } else {
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < kComps; ++j)
         th1[j] = (p.method == 1 ? w[0][j] : (w[0][j] + w[1][j]) / R(2)) * dt;
-      U = matmul(Exp<R, N>::apply(th1, p.n_squares), U);
+      U = matmul(Exp<R, N>::apply(th1, p.n_squares, full), U);
     }
   }
   // leave the rotating frame: U_k = diag(exp(-i m omega_r Dt)) U_k^r
@@ -471,9 +583,10 @@ int solve(const OProblem* p, const R* params, const R* psi0, R* U, R* psi, R* ps
 template <int N>
 void exp_tangents(const double th[4], int tau, Mat<double, N>& E, Mat<double, N>& Ex,
                   Mat<double, N>& Ey) {
-  Dual<double> t[4] = {Dual<double>(th[0], 1, 0), Dual<double>(th[1], 0, 1), Dual<double>(th[2]),
-                       Dual<double>(th[3])};
-  Mat<Dual<double>, N> M = Exp<Dual<double>, N>::apply(t, tau);
+  Dual<double> t[kComps] = {Dual<double>(th[0], 1, 0), Dual<double>(th[1], 0, 1),
+                            Dual<double>(th[2]), Dual<double>(th[3]), Dual<double>(0.0),
+                            Dual<double>(0.0), Dual<double>(0.0), Dual<double>(0.0)};
+  Mat<Dual<double>, N> M = Exp<Dual<double>, N>::apply(t, tau, false);
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) {
       const cx<Dual<double>>& z = M.m[i][j];
@@ -561,7 +674,7 @@ void interval_adjoint(const OProblem& p, const double* params, int64_t k, const 
   const double tk = p.t_start + (double)k * Dt;
   double wr = 0.0;
   if (p.rotating_frame) {
-    double f[4];
+    double f[kComps];
     field<double>(p, params, tk + Dt / 2.0, f);
     wr = two_pi<double>() * f[2];
   }
@@ -580,7 +693,7 @@ void interval_adjoint(const OProblem& p, const double* params, int64_t k, const 
     for (int i = 0; i < 2; ++i) {
       const double tau_i = ((double)l + cnode[i]) * dt;
       st.tau[i] = tau_i;
-      double f[4];
+      double f[kComps];
       field<double>(p, params, tk + tau_i, f);
       for (int j = 0; j < 4; ++j) w[i][j] = two_pi<double>() * f[j];
       cx<double> xy = cx<double>(w[i][0], w[i][1]) * expi(-(wr * tau_i));
@@ -667,8 +780,8 @@ extern "C" {
 void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int oracle_get_threads(void) { return omp_get_max_threads(); }
 
-void oracle_field(const OProblem* p, const double* params, double t, double* out4) {
-  field<double>(*p, params, t, out4);
+void oracle_field(const OProblem* p, const double* params, double t, double* out8) {
+  field<double>(*p, params, t, out8);
 }
 
 void oracle_exp_half(const double* th3, double* out8) {
@@ -681,6 +794,14 @@ void oracle_exp_one(const double* th4, int tau, double* out18) {
 
 void oracle_lie_trotter_residual(const double* th4, int tau, double* out18) {
   store<double, 3>(lie_trotter_residual<double>(th4, tau), out18);
+}
+
+void oracle_exp_full(const double* th8, int tau, double* out18) {
+  store<double, 3>(exp_full<double>(th8, tau), out18);
+}
+
+void oracle_basis_operator(int j, double* out18) {
+  store<double, 3>(basis_operator<double>(j), out18);
 }
 
 int oracle_operators(const OProblem* p, const double* params, int64_t k0, int64_t count,
@@ -738,6 +859,7 @@ int oracle_adjoint_population(const OProblem* p, const double* params, const dou
   if (!p || p->n_samples < 1 || p->n_fine < 1 || m < 0 || m > p->spin_twice) return 1;
   if (p->method != 0) return 3;
   if (p->field_fn) return 4;
+  if (full_basis(*p)) return 5;
   for (int i = 0; i < p->n_terms; ++i) {
     const OTerm& t = p->terms[i];
     const bool slots = t.a_slot >= 0 || t.f_slot >= 0 || t.phi_slot >= 0 || t.seg_a_slot >= 0 ||

@@ -97,6 +97,8 @@ def lib():
         L.oracle_exp_half.argtypes = [dp, dp]
         L.oracle_exp_one.argtypes = [dp, C.c_int, dp]
         L.oracle_lie_trotter_residual.argtypes = [dp, C.c_int, dp]
+        L.oracle_exp_full.argtypes = [dp, C.c_int, dp]
+        L.oracle_basis_operator.argtypes = [C.c_int, dp]
         L.oracle_operators.argtypes = [C.POINTER(_Problem), dp, C.c_int64, C.c_int64, dp]
         L.oracle_operators.restype = C.c_int
         L.oracle_states.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp]
@@ -168,9 +170,9 @@ def get_threads() -> int:
 
 
 def field(prob, t: float, field_fn=None) -> np.ndarray:
-    """Field functions (f_x, f_y, f_z, f_q) in Hz at time t."""
+    """Field functions (f_x, f_y, f_z, f_q, f_u1, f_u2, f_v1, f_v2) in Hz at time t."""
     pk = _Packed(prob, field_fn)
-    out = np.zeros(4)
+    out = np.zeros(8)
     pk.call(lib().oracle_field, C.byref(pk.p), _dp(pk.params), float(t), _dp(out))
     return out
 
@@ -192,6 +194,23 @@ def exp_one(theta, tau: int) -> np.ndarray:
     th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64)[:4])
     out = np.zeros(18)
     lib().oracle_exp_one(_dp(th), int(tau), _dp(out))
+    return _cmat(out, 3).copy()
+
+
+def exp_full(theta, tau: int) -> np.ndarray:
+    """Full su(3) basis: exp(-i sum_j theta_j A_j) over (J_x, J_y, J_z, Q, U_1,
+    U_2, V_1, V_2) by scaling and squaring (degree-4 Taylor residual of the
+    2^-tau step, then tau residual squarings)."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64)[:8])
+    out = np.zeros(18)
+    lib().oracle_exp_full(_dp(th), int(tau), _dp(out))
+    return _cmat(out, 3).copy()
+
+
+def basis_operator(j: int) -> np.ndarray:
+    """The spin-1 basis operator A_j, j = 0..7: J_x, J_y, J_z, Q, U_1, U_2, V_1, V_2."""
+    out = np.zeros(18)
+    lib().oracle_basis_operator(int(j), _dp(out))
     return _cmat(out, 3).copy()
 
 
@@ -278,6 +297,8 @@ def adjoint_population(prob, m: int) -> tuple[float, np.ndarray]:
         raise ValueError("gradients need parameter slots on x and y terms only")
     if rc == 3:
         raise ValueError("gradients need the CF4 method")
+    if rc == 5:
+        raise ValueError("gradients are not defined for the full su(3) basis")
     if rc:
         raise ValueError("oracle_adjoint_population: bad arguments")
     return float(loss[0]), grad[:pk.p.n_params].copy()

@@ -43,6 +43,10 @@ import numpy as np
 CONST, COS, SIN, PWC, PWC_COS, PWC_SIN = 0, 1, 2, 3, 4, 5
 # field components
 X, Y, Z, Q = 0, 1, 2, 3
+# spin-1 full su(3) basis: the Delta m = +-2 quadrupoles U_1 = J_x^2 - J_y^2,
+# U_2 = J_x J_y + J_y J_x and the Delta m = +-1 quadrupoles V_1 = J_z J_x + J_x J_z,
+# V_2 = J_y J_z + J_z J_y
+U1, U2, V1, V2 = 4, 5, 6, 7
 # integration methods: commutator-free fourth-order Magnus (the solver's), and
 # the two Euler-family sampling methods the paper compares it with
 CF4, MIDPOINT, HEUN = 0, 1, 2
