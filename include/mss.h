@@ -87,7 +87,22 @@ typedef enum mss_term_kind {
   MSS_TERM_PWC_SIN = 5
 } mss_term_kind;
 
-typedef enum mss_component { MSS_X = 0, MSS_Y = 1, MSS_Z = 2, MSS_Q = 3 } mss_component;
+/* Field components: the spin operators J_x, J_y, J_z and the quadrupole Q
+ * (spin-1), and for spin-1 in the full su(3) basis (Sec. "Spin-one": the
+ * paper adds w_u1 U_1 + w_u2 U_2 + w_v1 V_1 + w_v2 V_2 with operators from
+ * a reference it does not print) the Cartesian quadrupoles
+ * U_1 = J_x^2 - J_y^2, U_2 = J_x J_y + J_y J_x (Delta m = 2) and
+ * V_1 = J_z J_x + J_x J_z, V_2 = J_y J_z + J_z J_y (Delta m = 1).  A spin-1
+ * problem with a term on U_1, U_2, V_1 or V_2 runs the full-basis
+ * exponentiator: exp(-i G) by scaling and squaring, the residual of
+ * exp(-i G / 2^tau) from its degree-4 Taylor polynomial, then the tau
+ * residual squarings (n_squares); in the rotating frame (u1 + i u2) turns
+ * with e^{-2i w_r t} and (v1 + i v2) with e^{-i w_r t}.  Such problems
+ * have no adjoint and no specialised sampler (MSS_E_UNSUPPORTED). */
+typedef enum mss_component {
+  MSS_X = 0, MSS_Y = 1, MSS_Z = 2, MSS_Q = 3,
+  MSS_U1 = 4, MSS_U2 = 5, MSS_V1 = 6, MSS_V2 = 7
+} mss_component;
 
 typedef struct mss_term {
   int32_t kind;          /* mss_term_kind */

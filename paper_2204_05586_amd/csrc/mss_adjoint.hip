@@ -678,6 +678,9 @@ mss_status mss_adjoint_plan_create(int32_t n, const mss_problem* problems, const
     }
     if (q.method != MSS_CF4)
       return api_fail(MSS_E_UNSUPPORTED, "simulation %d: gradients need the CF4 method", i);
+    if (api_full_basis(&q))
+      return api_fail(MSS_E_UNSUPPORTED,
+                      "simulation %d: gradients are not defined for the full su(3) basis", i);
     if (level_m < 0 || level_m > q.spin_twice)
       return api_fail(MSS_E_INVALID, "simulation %d: level %d outside 0..%d", i, level_m,
                       q.spin_twice);

@@ -140,9 +140,10 @@ mss_status validate_terms(int spin_twice, const mss_term* terms, int n_terms, in
     const mss_term& t = terms[i];
     if (t.kind < MSS_TERM_CONST || t.kind > MSS_TERM_PWC_SIN)
       return api_fail(MSS_E_INVALID, "term %d: unknown kind %d", i, t.kind);
-    if (t.comp < 0 || t.comp > 3) return api_fail(MSS_E_INVALID, "term %d: comp must be 0..3", i);
-    if (t.comp == MSS_Q && spin_twice != 2)
-      return api_fail(MSS_E_INVALID, "term %d: the quadrupole component needs spin-1", i);
+    if (t.comp < 0 || t.comp > MSS_V2)
+      return api_fail(MSS_E_INVALID, "term %d: comp must be 0..7", i);
+    if (t.comp >= MSS_Q && spin_twice != 2)
+      return api_fail(MSS_E_INVALID, "term %d: the quadrupole components need spin-1", i);
     if (!finite(t.a) || !finite(t.f) || !finite(t.phi))
       return api_fail(MSS_E_INVALID, "term %d: a, f, phi must be finite", i);
     if (isnan(t.t_on) || isnan(t.t_off)) return api_fail(MSS_E_INVALID, "term %d: NaN window", i);
@@ -196,6 +197,12 @@ int api_device_cu_count() { return device_cu_count(); }
 int api_plan_slices(int64_t K, int32_t L, int cu) { return plan_slices(K, L, cu); }
 int api_ilog2(int x) { return ilog2(x); }
 mss_status api_validate_problem(const mss_problem* p) { return validate_problem(p); }
+bool api_full_basis(const mss_problem* p) {
+  if (p->spin_twice != 2) return false;
+  for (int i = 0; i < p->n_terms; ++i)
+    if (p->terms[i].comp >= MSS_U1) return true;
+  return false;
+}
 mss_status api_validate_terms(int spin_twice, const mss_term* terms, int n_terms, int n_params) {
   return validate_terms(spin_twice, terms, n_terms, n_params);
 }
@@ -343,6 +350,7 @@ mss_status mss_integrate(const mss_problem* p, const double* params, double* U, 
   a.g.tau = p->spin_twice == 2 ? p->n_squares : 0;
   a.g.frame = p->rotating_frame;
   a.g.method = p->method;
+  a.g.full = api_full_basis(p) ? 1 : 0;
   api_plan_lane_segments(a.g, S, given, integrate_slots(p->spin_twice + 1, B));
   hipError_t e = launch_integrate(p->spin_twice + 1, a, B, (hipStream_t)stream);
   if (e != hipSuccess) return api_hip_fail(e, "integrate launch");

@@ -30,14 +30,27 @@ struct FieldProgram {
   mss_term t[MSS_MAX_TERMS];
 };
 
+// Does a field source provide the full su(3) basis (the field-program
+// interpreter does; a user field function gives four components)?
+template <class T, class = void>
+struct has_full_basis {
+  static constexpr bool value = false;
+};
+template <class T>
+struct has_full_basis<T, decltype((void)T::kFullBasis)> {
+  static constexpr bool value = T::kFullBasis;
+};
+
 // Term sources for the interpreter: the kernel-argument program of a single
 // simulation, or a slice of a term table in device memory (batches).
 struct ArgTerms {
+  static constexpr bool kFullBasis = true;  // field programs may use all eight components
   const FieldProgram& fp;
   __device__ __forceinline__ int size() const { return fp.n_terms; }
   __device__ __forceinline__ const mss_term& operator[](int i) const { return fp.t[i]; }
 };
 struct TableTerms {
+  static constexpr bool kFullBasis = true;
   const mss_term* __restrict__ t;
   int n;
   __device__ __forceinline__ int size() const { return n; }
@@ -589,23 +602,241 @@ __device__ __forceinline__ void exit_frame(double wr, double Dt, Mat<N>& U) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// spin-1 in the full su(3) basis: components x, y, z, q, u1, u2, v1, v2 of
+// H = 2 pi (f_x J_x + f_y J_y + f_z J_z + f_q Q + f_u1 U_1 + f_u2 U_2 + f_v1 V_1
+// + f_v2 V_2), with U_1 = J_x^2 - J_y^2, U_2 = J_x J_y + J_y J_x (Delta m = 2)
+// and V_1 = J_z J_x + J_x J_z, V_2 = J_y J_z + J_z J_y (Delta m = 1).  A
+// spin-1 problem takes this path when a term is on u1, u2, v1 or v2.
+// ---------------------------------------------------------------------------
+constexpr int kFullComps = 8;
+
+// The field at time t over the eight components, terms summed in list order
+// (the interpreter's arithmetic of field_eval).
+template <class Terms>
+__device__ __forceinline__ void field_eval_full(const Terms& fp, const double* __restrict__ params,
+                                                double t, double f[kFullComps]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int j = 0; j < kFullComps; ++j) f[j] = 0.0;
+  const int nt = fp.size();
+  for (int n = 0; n < nt; ++n) {
+    const mss_term& tm = fp[n];
+    if (!(tm.t_on < t && t < tm.t_off)) continue;
+    double amp = tm.a_slot >= 0 ? params[tm.a_slot] : tm.a;
+    const double fr = tm.f_slot >= 0 ? params[tm.f_slot] : tm.f;
+    double ph = tm.phi_slot >= 0 ? params[tm.phi_slot] : tm.phi;
+    const int kind = tm.kind;
+    if (kind >= MSS_TERM_PWC) {
+      const double x = (t - tm.seg_t0) / tm.seg_len;
+      const double fl = floor(x);
+      int s = fl < 0.0 ? 0 : (fl > (double)(tm.n_seg - 1) ? tm.n_seg - 1 : (int)fl);
+      if (tm.seg_a_slot >= 0) amp = params[tm.seg_a_slot + s];
+      if (tm.seg_phi_slot >= 0) ph = params[tm.seg_phi_slot + s];
+    }
+    double v;
+    if (kind == MSS_TERM_CONST || kind == MSS_TERM_PWC) {
+      v = amp;
+    } else {
+      const double ft = fr * t;
+      const double x = kTwoPi * ft;
+      const double arg = x + ph;
+      double sn, cs;
+      sincos_cw(arg, &sn, &cs);
+      v = amp * ((kind == MSS_TERM_COS || kind == MSS_TERM_PWC_COS) ? cs : sn);
+    }
+    switch (tm.comp) {
+      case 0: f[0] = f[0] + v; break;
+      case 1: f[1] = f[1] + v; break;
+      case 2: f[2] = f[2] + v; break;
+      case 3: f[3] = f[3] + v; break;
+      case 4: f[4] = f[4] + v; break;
+      case 5: f[5] = f[5] + v; break;
+      case 6: f[6] = f[6] + v; break;
+      default: f[7] = f[7] + v; break;
+    }
+  }
+}
+
+// Node field in the rotating frame: (x + i y) and (v1 + i v2) times
+// e^{-i wr tau}, (u1 + i u2) times e^{-2i wr tau} (Delta m = 1 and 2 under
+// rotations about z), z - wr; (c, s) = (cos, sin)(wr tau).
+__device__ __forceinline__ void frame_full(double w[kFullComps], double c, double s, double wr) {
+#pragma clang fp contract(off)
+  const double c2 = c * c - s * s, s2 = 2.0 * (c * s);
+  const double xr = w[0] * c + w[1] * s, xi = w[1] * c - w[0] * s;
+  const double ur = w[4] * c2 + w[5] * s2, ui = w[5] * c2 - w[4] * s2;
+  const double vr = w[6] * c + w[7] * s, vi = w[7] * c - w[6] * s;
+  w[0] = xr;
+  w[1] = xi;
+  w[2] = w[2] - wr;
+  w[4] = ur;
+  w[5] = ui;
+  w[6] = vr;
+  w[7] = vi;
+}
+
+template <class Terms>
+__device__ __forceinline__ void cf4_angles_full(const Terms& fp, const double* __restrict__ params,
+                                                double tk, int l, double dt, double wr,
+                                                const NodeRotations& rot,
+                                                double th1[kFullComps], double th2[kFullComps]) {
+#pragma clang fp contract(off)
+  double w[2][kFullComps];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double tau_i = ((double)l + (i == 0 ? kNode1 : kNode2)) * dt;
+    double f[kFullComps];
+    field_eval_full(fp, params, tk + tau_i, f);
+#pragma unroll
+    for (int j = 0; j < kFullComps; ++j) w[i][j] = kTwoPi * f[j];
+    if (wr != 0.0) frame_full(w[i], rot.c[i], rot.s[i], wr);
+  }
+#pragma unroll
+  for (int j = 0; j < kFullComps; ++j) {
+    th1[j] = (kWPlus * w[0][j] + kWMinus * w[1][j]) * dt;
+    th2[j] = (kWMinus * w[0][j] + kWPlus * w[1][j]) * dt;
+  }
+}
+
+template <class Terms>
+__device__ __forceinline__ void euler_angles_full(const Terms& fp,
+                                                  const double* __restrict__ params, double tk,
+                                                  int l, double dt, double wr, int method,
+                                                  double th[kFullComps]) {
+#pragma clang fp contract(off)
+  const int nn = method == 1 ? 1 : 2;
+  double w[2][kFullComps] = {};
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {  // a fixed trip count keeps w in registers
+    if (i >= nn) break;
+    const double c = method == 1 ? 0.5 : (i == 0 ? 0.0 : 1.0);
+    const double tau_i = ((double)l + c) * dt;
+    double f[kFullComps];
+    field_eval_full(fp, params, tk + tau_i, f);
+#pragma unroll
+    for (int j = 0; j < kFullComps; ++j) w[i][j] = kTwoPi * f[j];
+    if (wr != 0.0) {
+      double s, cs;
+      sincos_cw(wr * tau_i, &s, &cs);
+      frame_full(w[i], cs, s, wr);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kFullComps; ++j)
+    th[j] = (method == 1 ? w[0][j] : (w[0][j] + w[1][j]) / 2.0) * dt;
+}
+
+// One general residual squaring y = (x + 2I) x.
+__device__ __forceinline__ void residual_square_full(const Mat<3>& x, Mat<3>& y) {
+  Mat<3> b = x;
+  b.r[0][0] += 2.0;
+  b.r[1][1] += 2.0;
+  b.r[2][2] += 2.0;
+  matmul<3>(b, x, y);
+}
+
+// exp(-i G), G = sum_j theta_j A_j over the full basis, by scaling and
+// squaring: X = -i G / n with n = 2^tau, the residual of exp(X) from its
+// degree-4 Taylor polynomial in Horner form, X (I + X/2 (I + X/3 (I + X/4)))
+// (no identity term, nothing cancels), then tau residual squarings, I + a.
+__device__ __forceinline__ void exp_full(const double th[kFullComps], int tau, Mat<3>& E) {
+  const double ninv = ldexp(1.0, -tau);
+  // G entry by entry: J_x, J_y, V_1, V_2 couple neighbouring levels (1/sqrt 2),
+  // U_1, U_2 the outer pair; J_z and Q on the diagonal.
+  const double g00 = th[2] + th[3] * (1.0 / 3.0);
+  const double g11 = th[3] * (-2.0 / 3.0);
+  const double g22 = -th[2] + th[3] * (1.0 / 3.0);
+  const double g01r = kRsqrt2 * (th[0] + th[6]), g01i = -kRsqrt2 * (th[1] + th[7]);
+  const double g12r = kRsqrt2 * (th[0] - th[6]), g12i = -kRsqrt2 * (th[1] - th[7]);
+  const double g02r = th[4], g02i = -th[5];
+  // X = -i G / n: -i (gr + i gi) = gi - i gr; the lower triangle holds conj(G)
+  Mat<3> X;
+  X.r[0][0] = 0.0;  X.i[0][0] = -g00 * ninv;
+  X.r[1][1] = 0.0;  X.i[1][1] = -g11 * ninv;
+  X.r[2][2] = 0.0;  X.i[2][2] = -g22 * ninv;
+  X.r[0][1] = g01i * ninv;   X.i[0][1] = -g01r * ninv;
+  X.r[1][0] = -g01i * ninv;  X.i[1][0] = -g01r * ninv;
+  X.r[1][2] = g12i * ninv;   X.i[1][2] = -g12r * ninv;
+  X.r[2][1] = -g12i * ninv;  X.i[2][1] = -g12r * ninv;
+  X.r[0][2] = g02i * ninv;   X.i[0][2] = -g02r * ninv;
+  X.r[2][0] = -g02i * ninv;  X.i[2][0] = -g02r * ninv;
+  Mat<3> a, t;
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      a.r[p][q] = X.r[p][q] * 0.25 + (p == q ? 1.0 : 0.0);
+      a.i[p][q] = X.i[p][q] * 0.25;
+    }
+  const double inv_k[2] = {1.0 / 3.0, 0.5};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    matmul<3>(X, a, t);
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        a.r[p][q] = t.r[p][q] * inv_k[h] + (p == q ? 1.0 : 0.0);
+        a.i[p][q] = t.i[p][q] * inv_k[h];
+      }
+  }
+  matmul<3>(X, a, t);
+  for (int s = 0; s + 2 <= tau; s += 2) {
+    residual_square_full(t, a);
+    residual_square_full(a, t);
+  }
+  if (tau & 1) {
+    residual_square_full(t, a);
+    t = a;
+  }
+  E = t;
+  E.r[0][0] += 1.0;
+  E.r[1][1] += 1.0;
+  E.r[2][2] += 1.0;
+}
+
 // Operator of one interval (rows a1-a9) computed by S = 2^sl cooperating
 // lanes: slice s integrates fine steps [s L / S, (s + 1) L / S) and the
 // partial products are combined in order with wave shuffles; the full
 // U_k (frame exit applied) ends up in the lane with s == 0.  Every lane of
 // the wave must call this (the shuffles need the whole wave).
-template <int N, class Terms>
+template <int N, bool FULL = false, class Terms>
 __device__ __forceinline__ void interval_operator(const Terms& terms, const double* __restrict__ params,
                                                   double t_start, double Dt, double dt, int L,
                                                   int tau, int frame, int method, int64_t k, int s,
                                                   int sl, bool active, Mat<N>& U, double* tk_out) {
+  static_assert(!FULL || N == 3, "the full basis is spin-1 only");
   set_identity<N>(U);
   double tk = 0.0, wr = 0.0;
   if (active) {
     interval_setup(terms, params, t_start, Dt, k, frame, &tk, &wr);
     const int l0 = (int)(((int64_t)s * L) >> sl);
     const int l1 = (int)(((int64_t)(s + 1) * L) >> sl);
-    if (method == 0) {
+    if constexpr (FULL) {
+      if (method == 0) {
+        NodeRotations rot;
+        if (wr != 0.0) rot.start(wr, l0, dt);
+        for (int l = l0; l < l1; ++l) {
+          double th1[kFullComps], th2[kFullComps];
+          cf4_angles_full(terms, params, tk, l, dt, wr, rot, th1, th2);
+          if (wr != 0.0) rot.advance();
+          Mat<3> E;
+          exp_full(th1, tau, E);
+          premultiply<3>(E, U);
+          exp_full(th2, tau, E);
+          premultiply<3>(E, U);
+        }
+      } else {
+        for (int l = l0; l < l1; ++l) {
+          double th[kFullComps];
+          euler_angles_full(terms, params, tk, l, dt, wr, method, th);
+          Mat<3> E;
+          exp_full(th, tau, E);
+          premultiply<3>(E, U);
+        }
+      }
+    } else if (method == 0) {
       NodeRotations rot;
       if (wr != 0.0) rot.start(wr, l0, dt);
       for (int l = l0; l < l1; ++l) {
@@ -657,7 +888,7 @@ struct IntervalGrid {
   int32_t method;
   int32_t n_seg;         // 1 or 2
   int32_t seg_sl[2];     // log2 of the lane-slices per interval
-  int32_t pad;
+  int32_t full;          // spin-1 in the full su(3) basis
   int64_t seg_k0[2];     // first interval of each segment
   int64_t seg_w0[2];     // first wave of each segment
 };
@@ -678,8 +909,17 @@ __device__ __forceinline__ void integrate_lanes(const Terms& terms, const Interv
   const bool active = k < (j + 1 < g.n_seg ? g.seg_k0[j + 1] : g.K);
   Mat<N> U;
   double tk;
-  interval_operator<N>(terms, g.params, g.t_start, g.dt_out, g.dt, g.L, g.tau, g.frame, g.method,
-                       k, s, sl, active, U, &tk);
+  bool done = false;
+  if constexpr (N == 3 && has_full_basis<Terms>::value) {
+    if (g.full) {
+      interval_operator<3, true>(terms, g.params, g.t_start, g.dt_out, g.dt, g.L, g.tau, g.frame,
+                                 g.method, k, s, sl, active, U, &tk);
+      done = true;
+    }
+  }
+  if (!done)
+    interval_operator<N>(terms, g.params, g.t_start, g.dt_out, g.dt, g.L, g.tau, g.frame,
+                         g.method, k, s, sl, active, U, &tk);
   if (active && s == 0) {
     store_mat<N>(g.U + (size_t)k * 2 * N * N, U);
     if (g.time) g.time[k] = tk;

@@ -26,6 +26,8 @@ mss_status api_ok();
 mss_status api_hip_fail(hipError_t e, const char* what);
 std::string api_last_error_copy();
 mss_status api_validate_problem(const mss_problem* p);
+// a spin-1 problem with a term on U_1, U_2, V_1 or V_2 (the full su(3) basis)
+bool api_full_basis(const mss_problem* p);
 // the term checks of api_validate_problem for a term list on its own
 mss_status api_validate_terms(int spin_twice, const mss_term* terms, int n_terms, int n_params);
 // a problem run with a sampler: its parameter vector covers what the

@@ -249,6 +249,9 @@ mss_status mss_sampler_create_for_terms(const mss_term* terms, int32_t n_terms,
       if (t.seg_phi_slot >= 0) need = std::max(need, t.seg_phi_slot + t.n_seg);
     }
     quad = quad || t.comp == MSS_Q;
+    if (t.comp >= MSS_U1 && t.comp <= MSS_V2)
+      return api_fail(MSS_E_UNSUPPORTED,
+                      "term %d: full su(3) components are interpreted, not compiled in", i);
   }
   mss_status st = api_validate_terms(2, terms, n_terms, need);
   if (st != MSS_OK) return st;

@@ -163,6 +163,7 @@ void WorkSet::add(const mss_problem& p, int slices_log2, int64_t k_first, int64_
   d.tau = p.spin_twice == 2 ? p.n_squares : 0;
   d.frame = p.rotating_frame;
   d.method = p.method;
+  d.full = api_full_basis(&p) ? 1 : 0;
   d.slices_log2 = slices_log2;
   d.top = scan ? scan_top(p.n_samples, 64 * scan_e) : -1;
   if (last_terms_ && last_n_terms_ == p.n_terms &&

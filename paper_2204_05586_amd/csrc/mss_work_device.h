@@ -22,7 +22,7 @@ struct SimDesc {
   double* scan_ws;     // scan levels 1..top: per level [n_l][N][N] then [n_l][N]
   int32_t spin_twice, n_terms, term_off, n_fine;
   int32_t tau, frame, slices_log2, top;  // top: scan levels above 0; -1: no scan
-  int32_t method, pad;
+  int32_t method, full;  // full: spin-1 in the full su(3) basis
 };
 
 struct IntegrateWorkArgs {
@@ -51,8 +51,18 @@ __device__ __forceinline__ void work_item(const IntegrateWorkArgs& A, const SimD
   const int64_t k = s.k_first + j;
   Mat<N> U;
   double tk;
-  interval_operator<N>(source(A, s), s.params, s.t_start, s.dt_out, s.dt, s.n_fine, s.tau,
-                       s.frame, s.method, k, slice, sl, active, U, &tk);
+  using Terms = decltype(source(A, s));
+  bool done = false;
+  if constexpr (N == 3 && has_full_basis<Terms>::value) {
+    if (s.full) {
+      interval_operator<3, true>(source(A, s), s.params, s.t_start, s.dt_out, s.dt, s.n_fine,
+                                 s.tau, s.frame, s.method, k, slice, sl, active, U, &tk);
+      done = true;
+    }
+  }
+  if (!done)
+    interval_operator<N>(source(A, s), s.params, s.t_start, s.dt_out, s.dt, s.n_fine, s.tau,
+                         s.frame, s.method, k, slice, sl, active, U, &tk);
   if (active && slice == 0) store_mat<N>(s.U + (size_t)k * 2 * N * N, U);
 }
 

@@ -419,10 +419,11 @@ class Sampler:
 def specialise(problems) -> "Optional[tuple[Sampler, list]]":
     """When every problem has the same term list, that field program
     compiled into its own integrator and the problems without their terms
-    (what a sampler runs); None otherwise.  The caller owns the sampler."""
+    (what a sampler runs); None otherwise, and for full su(3) programs.  The
+    caller owns the sampler."""
     problems = list(problems)
-    if not problems:
-        return None
+    if not problems or any(int(t.comp) >= 4 for t in problems[0].terms):
+        return None  # full su(3) programs are interpreted
     key = _terms_key(problems[0].terms)
     if any(_terms_key(p.terms) != key for p in problems[1:]):
         return None

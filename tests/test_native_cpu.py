@@ -63,6 +63,11 @@ def test_validation_rejects_bad_problems():
     _bad(good.replace(terms=[W.Term(W.PWC, W.X, n_seg=4, seg_len=0.0)]), "seg_len")
     _bad(good.replace(terms=[W.Term(W.CONST, W.X, a=float("nan"))]), "finite")
     _bad(good.replace(terms=[W.Term(W.CONST, W.X)] * 33), "terms")
+    # full su(3) components: spin-1 only, and no component past V_2
+    for c in (W.U1, W.U2, W.V1, W.V2):
+        _bad(half.replace(terms=half.terms + [W.Term(W.CONST, c, a=1.0)]), "quadrupole")
+        native.validate(good.replace(terms=good.terms + [W.Term(W.COS, c, a=1.0, f=2.0)]))
+    _bad(good.replace(terms=[W.Term(W.CONST, 8, a=1.0)]), "comp")
 
 
 def test_workspace_sizes():
@@ -164,6 +169,17 @@ def test_sampler_for_terms_rejects_invalid_terms():
     h = C.c_void_p()
     assert native.lib().mss_sampler_create_for_terms(None, 1, C.byref(h)) == native.MSS_E_INVALID
     assert native.lib().mss_sampler_create_for_terms(None, 0, None) == native.MSS_E_INVALID
+
+
+def test_full_basis_is_interpreted_and_has_no_adjoint():
+    """Field programs on U_1, U_2, V_1, V_2 are not compiled into samplers (the
+    batch plan keeps interpreting them) and have no adjoint."""
+    T = W.Term
+    terms = [T(W.CONST, W.Z, a=1e3), T(W.COS, W.V1, a=10.0, f=1e3)]
+    with pytest.raises(native.MssError, match="su\\(3\\)") as e:
+        native.Sampler.for_terms(terms)
+    assert e.value.status == native.MSS_E_UNSUPPORTED
+    assert native.specialise([W.Problem(2, terms, 0.0, 1e-6, 10, 2, 28, True)]) is None
 
 
 def test_sampler_for_terms_checks_problems_before_launch():
