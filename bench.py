@@ -38,9 +38,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # sources are unchanged.
 MEASURED_TRAFFIC = {
     ("mss_user_work_integrate", "batched_sensing"): {
-        "src": "e84e5d272c896f57",
-        "fetch_kib": 4510.8125, "write_kib": 64034495.25,
-        "bytes": int(round((4510.8125 * 2.000 + 64034495.25 * 1.000) * 1024)),
+        "src": "1cc4790fc03a6c44",
+        "fetch_kib": 4549.125, "write_kib": 64034595.375,
+        "bytes": int(round((4549.125 * 2.000 + 64034595.375 * 1.000) * 1024)),
     },
 }
 
