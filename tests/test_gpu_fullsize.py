@@ -21,13 +21,15 @@ def torch_dev():
 
 def test_batched_sensing_full(torch_dev, oracle):
     """All 4096 uneven spin-1 simulations (4.5e9 CF4 steps) in one batch,
-    states only, autotuned launch; the longest, the shortest and 4 seeded
-    simulations against the oracle."""
+    states only, the bench's configuration (the shared field program
+    compiled into the integrator, autotuned launch); the longest, the
+    shortest and 4 seeded simulations against the oracle."""
     import torch
     from paper_2204_05586_amd import autotune, native
     probs = W.batched_sensing(seed=2)
-    opts = autotune.tune(probs, cache_path=None, reps=2)
-    plan = native.BatchPlan(probs, **opts)
+    opts = autotune.tune(probs, cache_path=None, reps=2, specialize=True)
+    plan = native.BatchPlan(probs, specialize=True, **opts)
+    assert plan.specialized
     bufs = plan.allocate(store_u=False)
     print(f"[gpu] full batched sensing {plan.info()} options {opts}", flush=True)
     plan.run(bufs)
@@ -43,6 +45,32 @@ def test_batched_sensing_full(torch_dev, oracle):
         print(f"sim {i} K={probs[i].n_samples}: max |d| = {d:.3e}", flush=True)
         assert d <= TOL, (i, d)
     plan.close()
+
+
+def test_plain_sensing_full_compiled_field(torch_dev, oracle):
+    """The bench's plain leg at full size: 2e5 intervals x 10 CF4 steps with
+    the field program compiled into the integrator, the library's default
+    launch, then the scan; every state and operator against the oracle."""
+    import torch
+    from paper_2204_05586_amd import native
+    prob = W.spin_one_sensing()
+    s = native.Sampler.for_terms(prob.terms)
+    K, N = prob.n_samples, prob.dim
+    U = torch.empty((K, N, N), dtype=torch.complex128, device="cuda")
+    psi = torch.empty((K, N), dtype=torch.complex128, device="cuda")
+    fin = torch.empty((N,), dtype=torch.complex128, device="cuda")
+    ws = native.alloc_workspace(native.propagate_workspace_size(prob.spin_twice, K))
+    print(f"[gpu] plain sensing, compiled field, K={K}", flush=True)
+    s.integrate(prob.replace(terms=[]), native.device_params(prob), U)
+    native.propagate(prob.spin_twice, U, native.device_state(prob.psi0), psi, fin, ws)
+    torch.cuda.synchronize()
+    ref = oracle.solve(prob, want_U=True)
+    d = max(np.max(np.abs(psi.cpu().numpy() - ref["psi"])),
+            np.max(np.abs(fin.cpu().numpy() - ref["psi_final"])),
+            np.max(np.abs(U.cpu().numpy() - ref["U"])))
+    print(f"plain sensing, compiled field: max |d| = {d:.3e}", flush=True)
+    assert d <= TOL
+    s.close()
 
 
 def test_serving_stream_full(torch_dev, oracle):
