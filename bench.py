@@ -332,6 +332,105 @@ def bench_adjoint(n_inst: int, steps: int, warmup: int) -> dict:
             "forward_plus_adjoint_fine_steps_per_s": round(fine / dt, 1)}
 
 
+# The spin-1 sensing field written as a user field function (HIP source),
+# the way the paper's users write theirs: the f3 row's input.
+SENSING_USER_SOURCE = r"""
+__device__ void mss_user_field(double t, const double* p, double* f) {
+  double s, c;
+  mss::sincos_cw(mss::kTwoPi * (700e3 * t), &s, &c);
+  double fx = 2000.0 * c;
+  if (0.05 < t && t < 0.051) {
+    mss::sincos_cw(mss::kTwoPi * (1000.0 * t), &s, &c);
+    fx += 20.0 * s;
+  }
+  f[0] = fx;
+  f[2] = 700e3;
+  f[3] = 2.3;
+}
+"""
+
+
+def bench_next_rows(reps: int = 20) -> dict:
+    """The rows beyond the batched path, each timed with HIP events on the
+    2e5-interval spin-1 sensing simulation (inputs resident on the device):
+    f1 <J> of its states; f2 its midpoint and Heun samplings (field program
+    compiled in); f3 its field written as a user sampler; f4 the same problem
+    in the full su(3) basis (a resonant V_1 drive added; interpreted)."""
+    import torch
+    from paper_2204_05586_amd import native, workloads as W
+    prob = W.spin_one_sensing()
+    K, N, tau = prob.n_samples, prob.dim, prob.n_squares
+    fine = prob.fine_steps
+    stream = torch.cuda.current_stream()
+    params = native.device_params(prob)
+    U = torch.empty((K, N, N), dtype=torch.complex128, device="cuda")
+
+    def timed(fn) -> float:
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(reps)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return statistics.mean(a.elapsed_time(b) for a, b in evs)
+
+    def alu(flops_per_step: int, ms: float) -> dict:
+        tf = flops_per_step * fine / (ms * 1e-3) / 1e12
+        return {"fine_steps_per_s": round(fine / (ms * 1e-3), 1), "integrate_ms": round(ms, 4),
+                "roofline": {"bound": "alu", "achieved": round(tf, 3),
+                             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4),
+                             "flops_per_fine_step": flops_per_step}}
+
+    out = {}
+    smp = native.Sampler.for_terms(prob.terms)
+    for name, method in (("midpoint", W.MIDPOINT), ("heun", W.HEUN)):
+        bare = prob.replace(terms=[], method=method)
+        ms = timed(lambda: smp.integrate(bare, params, U, stream=stream))
+        # one exponential of tau symmetric squarings and one product per fine step
+        out[f"f2_{name}"] = alu(96 * tau + 216, ms)
+    smp.close()
+    user = native.Sampler(SENSING_USER_SOURCE)
+    bare = prob.replace(terms=[])
+    ms = timed(lambda: user.integrate(bare, params, U, stream=stream))
+    out["f3_user_sampler"] = alu(spin_one_flops_per_fine_step(tau), ms)
+    user.close()
+    full = prob.replace(terms=list(prob.terms) + [W.Term(W.COS, W.V1, a=300.0, f=700e3)])
+    ms = timed(lambda: native.integrate(full, params, U, stream=stream))
+    # per exponential: the Taylor residual (3 products) and tau general
+    # squarings (27 complex multiply-adds = 216 flops each); two per step,
+    # plus the two products into U
+    out["f4_full_su3"] = alu(2 * (3 * 216 + tau * 216) + 2 * 216, ms)
+    psi = torch.empty((K, N), dtype=torch.complex128, device="cuda")
+    fin = torch.empty((N,), dtype=torch.complex128, device="cuda")
+    ws = native.alloc_workspace(native.propagate_workspace_size(prob.spin_twice, K))
+    native.integrate(prob, params, U, stream=stream)
+    native.propagate(prob.spin_twice, U, native.device_state(prob.psi0), psi, fin, ws,
+                     stream=stream)
+    ms = timed(lambda: native.spin_projection(psi, stream=stream))
+    gbs = K * (16 * N + 24) / (ms * 1e-3) / 1e9  # read the state, write <J_x>, <J_y>, <J_z>
+    psi0 = native.device_state(prob.psi0)
+    spin = torch.empty((K, 3), dtype=torch.float64, device="cuda")
+    ms_scan = timed(lambda: native.propagate(prob.spin_twice, U, psi0, psi, fin, ws,
+                                             stream=stream))
+    ms_fused = timed(lambda: native.propagate(prob.spin_twice, U, psi0, psi, fin, ws,
+                                              stream=stream, spin=spin))
+    out["f1_spin_projection"] = {"states_per_s": round(K / (ms * 1e-3), 1), "ms": round(ms, 4),
+                                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1),
+                                              "peak": 8000.0, "unit": "GB/s",
+                                              "frac": round(gbs / 8000.0, 4)},
+                                 # the scan alone, then with <J> formed in its last pass
+                                 "scan_ms": round(ms_scan, 4),
+                                 "scan_with_spin_ms": round(ms_fused, 4)}
+    del U, psi, ws, spin
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,6 +454,9 @@ def main():
                     help="target stream length per rate (requests = rate x seconds, <= 2000)")
     ap.add_argument("--adjoint-instances", type=int, default=1024,
                     help="instances of the control-gradient workload (0: skip)")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the f1-f4 measurements (spin projection, Euler samplings, "
+                         "user sampler, full su(3) basis)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -438,6 +540,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    next_rows = None
+    if not args.no_next_rows and args.plain_steps > 0:
+        next_rows = bench_next_rows()
+
     adjoint = None
     if args.adjoint_instances > 0:
         adjoint = bench_adjoint(args.adjoint_instances, 3, 1)
@@ -468,6 +574,7 @@ def main():
         **extra,
         "latency": serving,
         "adjoint": adjoint,
+        "next_rows": next_rows,
         "roofline": roofline,
         "cpu_baseline": base,
         "kernel_src": src_hash,

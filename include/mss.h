@@ -189,6 +189,15 @@ mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
                          const double* psi0, double* psi, double* psi_final, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* mss_propagate that also writes the expected spin projection of every
+ * state as the states are formed (the projection of mss_spin_projection,
+ * fused into the last pass of the product, so the states are not read
+ * back): spin: device [n_samples][3] doubles, required.  Same errors as
+ * mss_propagate, and MSS_E_INVALID for a NULL spin. */
+mss_status mss_propagate_spin(int32_t spin_twice, int64_t n_samples, const double* U,
+                              const double* psi0, double* psi, double* psi_final, double* spin,
+                              void* ws, size_t ws_bytes, void* stream);
+
 /* Expected spin projection <J_x>, <J_y>, <J_z> of each state (Sec.
  * "Quantum mechanics background": the measurable ensemble average of the
  * spin): out[3k + a] = psi_k^H J_a psi_k.  psi: device [n_samples][N]

@@ -272,6 +272,52 @@ int64_t api_grid_waves(const IntervalGrid& g) {
 }
 }  // namespace mss
 
+namespace {
+// The ordered product, with <J> of every state when spin is non-null.
+mss_status propagate(int32_t spin_twice, int64_t n_samples, const double* U, const double* psi0,
+                     double* psi, double* psi_final, double* spin, void* ws, size_t ws_bytes,
+                     void* stream) {
+  if (spin_twice != 1 && spin_twice != 2) return api_fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
+  if (n_samples < 1) return api_fail(MSS_E_INVALID, "n_samples must be >= 1");
+  if (!U || !psi0 || !psi) return api_fail(MSS_E_INVALID, "U, psi0 and psi are required");
+  const int N = spin_twice + 1;
+  const ScanLevels lv = plan_scan(N, n_samples);
+  if (lv.bytes > 0 && (!ws || ws_bytes < lv.bytes))
+    return api_fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", lv.bytes,
+                ws ? ws_bytes : (size_t)0);
+  hipStream_t st = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const double* M[8];
+  M[0] = U;
+  for (int l = 1; l <= lv.n_levels; ++l) M[l] = (const double*)(w + lv.agg_off[l]);
+  hipError_t e;
+  if (lv.n_levels == 2 && (lv.n[1] + kScanTile - 1) / kScanTile <= 16) {
+    // level 0 up, levels 1-2 in one workgroup, level 0 down
+    e = launch_scan_reduce(N, M[0], lv.n[0], (double*)M[1], st);
+    if (e == hipSuccess)
+      e = launch_scan_top(N, M[1], lv.n[1], psi0, (double*)(w + lv.state_off[1]), st);
+    if (e == hipSuccess)
+      e = launch_scan_apply(N, M[0], lv.n[0], (const double*)(w + lv.state_off[1]), psi,
+                            psi_final, st, spin);
+    if (e != hipSuccess) return api_hip_fail(e, "scan launch");
+    return api_ok();
+  }
+  for (int l = 0; l < lv.n_levels; ++l) {
+    e = launch_scan_reduce(N, M[l], lv.n[l], (double*)M[l + 1], st);
+    if (e != hipSuccess) return api_hip_fail(e, "scan reduce launch");
+  }
+  // top level: one tile entered with psi0
+  for (int l = lv.n_levels; l >= 0; --l) {
+    const double* start = (l == lv.n_levels) ? psi0 : (const double*)(w + lv.state_off[l + 1]);
+    double* before = (l == 0) ? psi : (double*)(w + lv.state_off[l]);
+    double* after = (l == 0) ? psi_final : nullptr;
+    e = launch_scan_apply(N, M[l], lv.n[l], start, before, after, st, l == 0 ? spin : nullptr);
+    if (e != hipSuccess) return api_hip_fail(e, "scan apply launch");
+  }
+  return api_ok();
+}
+}  // namespace
+
 extern "C" {
 
 const char* mss_status_str(mss_status s) {
@@ -357,47 +403,18 @@ mss_status mss_integrate(const mss_problem* p, const double* params, double* U, 
   return api_ok();
 }
 
+
 mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
                          const double* psi0, double* psi, double* psi_final, void* ws,
                          size_t ws_bytes, void* stream) {
-  if (spin_twice != 1 && spin_twice != 2) return api_fail(MSS_E_INVALID, "spin_twice must be 1 or 2");
-  if (n_samples < 1) return api_fail(MSS_E_INVALID, "n_samples must be >= 1");
-  if (!U || !psi0 || !psi) return api_fail(MSS_E_INVALID, "U, psi0 and psi are required");
-  const int N = spin_twice + 1;
-  const ScanLevels lv = plan_scan(N, n_samples);
-  if (lv.bytes > 0 && (!ws || ws_bytes < lv.bytes))
-    return api_fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", lv.bytes,
-                ws ? ws_bytes : (size_t)0);
-  hipStream_t st = (hipStream_t)stream;
-  char* w = (char*)ws;
-  const double* M[8];
-  M[0] = U;
-  for (int l = 1; l <= lv.n_levels; ++l) M[l] = (const double*)(w + lv.agg_off[l]);
-  hipError_t e;
-  if (lv.n_levels == 2 && (lv.n[1] + kScanTile - 1) / kScanTile <= 16) {
-    // level 0 up, levels 1-2 in one workgroup, level 0 down
-    e = launch_scan_reduce(N, M[0], lv.n[0], (double*)M[1], st);
-    if (e == hipSuccess)
-      e = launch_scan_top(N, M[1], lv.n[1], psi0, (double*)(w + lv.state_off[1]), st);
-    if (e == hipSuccess)
-      e = launch_scan_apply(N, M[0], lv.n[0], (const double*)(w + lv.state_off[1]), psi,
-                            psi_final, st);
-    if (e != hipSuccess) return api_hip_fail(e, "scan launch");
-    return api_ok();
-  }
-  for (int l = 0; l < lv.n_levels; ++l) {
-    e = launch_scan_reduce(N, M[l], lv.n[l], (double*)M[l + 1], st);
-    if (e != hipSuccess) return api_hip_fail(e, "scan reduce launch");
-  }
-  // top level: one tile entered with psi0
-  for (int l = lv.n_levels; l >= 0; --l) {
-    const double* start = (l == lv.n_levels) ? psi0 : (const double*)(w + lv.state_off[l + 1]);
-    double* before = (l == 0) ? psi : (double*)(w + lv.state_off[l]);
-    double* after = (l == 0) ? psi_final : nullptr;
-    e = launch_scan_apply(N, M[l], lv.n[l], start, before, after, st);
-    if (e != hipSuccess) return api_hip_fail(e, "scan apply launch");
-  }
-  return api_ok();
+  return propagate(spin_twice, n_samples, U, psi0, psi, psi_final, nullptr, ws, ws_bytes, stream);
+}
+
+mss_status mss_propagate_spin(int32_t spin_twice, int64_t n_samples, const double* U,
+                              const double* psi0, double* psi, double* psi_final, double* spin,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (!spin) return api_fail(MSS_E_INVALID, "spin is NULL");
+  return propagate(spin_twice, n_samples, U, psi0, psi, psi_final, spin, ws, ws_bytes, stream);
 }
 
 mss_status mss_spin_projection(int32_t spin_twice, int64_t n_samples, const double* psi,

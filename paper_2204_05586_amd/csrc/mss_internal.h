@@ -56,7 +56,7 @@ mss_status api_sampler_work_function(mss_sampler s, hipFunction_t* fn);
 hipError_t launch_integrate(int N, const IntegrateArgs& a, int block, hipStream_t st);
 hipError_t launch_scan_reduce(int N, const double* M, int64_t n, double* agg, hipStream_t st);
 hipError_t launch_scan_apply(int N, const double* M, int64_t n, const double* start, double* before,
-                             double* after_last, hipStream_t st);
+                             double* after_last, hipStream_t st, double* spin = nullptr);
 
 // levels 1 and 2 of a two-level single-sequence scan in one workgroup
 // (n1 level-1 elements in at most 16 tiles)

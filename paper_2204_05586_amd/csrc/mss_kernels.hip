@@ -30,13 +30,14 @@ template <int N>
 __global__ void __launch_bounds__(256) scan_apply_kernel(const double* __restrict__ M, int64_t n,
                                                          const double* __restrict__ start,
                                                          double* __restrict__ before,
-                                                         double* __restrict__ after_last) {
+                                                         double* __restrict__ after_last,
+                                                         double* __restrict__ spin) {
   const int lane = threadIdx.x & 63;
   const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   const bool valid = tile < ntiles;
   tile_apply<N, kScanPerLane>(M, n, tile, lane, valid, valid ? start + (size_t)tile * 2 * N : nullptr, before,
-                after_last);
+                after_last, spin);
 }
 
 // Levels 1 and 2 of a two-level scan in one workgroup (n1 <= 16 tiles):
@@ -74,25 +75,13 @@ __global__ void __launch_bounds__(256) spin_projection_kernel(const double* __re
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const double* v = psi + (size_t)k * 2 * N;
-  double jx, jy, jz;
-  if (N == 2) {
-    const double ar = v[0], ai = v[1], br = v[2], bi = v[3];
-    // <J_x> = Re(conj(a) b), <J_y> = Im(conj(a) b), <J_z> = (|a|^2 - |b|^2) / 2
-    jx = fma(ar, br, ai * bi);
-    jy = fma(ar, bi, -ai * br);
-    jz = 0.5 * (fma(ar, ar, ai * ai) - fma(br, br, bi * bi));
-  } else {
-    const double ar = v[0], ai = v[1], br = v[2], bi = v[3], cr = v[4], ci = v[5];
-    // conj(a) b + conj(b) c, scaled by sqrt 2 (twice the 1/sqrt 2 couplings)
-    const double sr = fma(ar, br, ai * bi) + fma(br, cr, bi * ci);
-    const double si = fma(ar, bi, -ai * br) + fma(br, ci, -bi * cr);
-    jx = 2.0 * kRsqrt2 * sr;
-    jy = 2.0 * kRsqrt2 * si;
-    jz = fma(ar, ar, ai * ai) - fma(cr, cr, ci * ci);
+  double vr[N], vi[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    vr[a] = v[2 * a];
+    vi[a] = v[2 * a + 1];
   }
-  out[3 * k] = jx;
-  out[3 * k + 1] = jy;
-  out[3 * k + 2] = jz;
+  project_spin<N>(vr, vi, out + 3 * k);
 }
 
 // ---------------------------------------------------------------------------
@@ -134,12 +123,14 @@ hipError_t launch_scan_reduce(int N, const double* M, int64_t n, double* agg, hi
 }
 
 hipError_t launch_scan_apply(int N, const double* M, int64_t n, const double* start, double* before,
-                             double* after_last, hipStream_t st) {
+                             double* after_last, hipStream_t st, double* spin) {
   const dim3 grid((unsigned)scan_grid(n)), block(256);
   if (N == 2)
-    hipLaunchKernelGGL(scan_apply_kernel<2>, grid, block, 0, st, M, n, start, before, after_last);
+    hipLaunchKernelGGL(scan_apply_kernel<2>, grid, block, 0, st, M, n, start, before, after_last,
+                       spin);
   else
-    hipLaunchKernelGGL(scan_apply_kernel<3>, grid, block, 0, st, M, n, start, before, after_last);
+    hipLaunchKernelGGL(scan_apply_kernel<3>, grid, block, 0, st, M, n, start, before, after_last,
+                       spin);
   return hipGetLastError();
 }
 

@@ -7,6 +7,32 @@
 
 namespace mss {
 
+// <J_a> = psi^H J_a psi of one state (a = x, y, z): spin-1/2 J = sigma/2;
+// spin-1 J_x, J_y with 1/sqrt 2 couplings between neighbouring levels,
+// J_z = diag(1, 0, -1).
+template <int N>
+__device__ __forceinline__ void project_spin(const double* vr, const double* vi, double* j3) {
+  double jx, jy, jz;
+  if (N == 2) {
+    const double ar = vr[0], ai = vi[0], br = vr[1], bi = vi[1];
+    // <J_x> = Re(conj(a) b), <J_y> = Im(conj(a) b), <J_z> = (|a|^2 - |b|^2) / 2
+    jx = fma(ar, br, ai * bi);
+    jy = fma(ar, bi, -ai * br);
+    jz = 0.5 * (fma(ar, ar, ai * ai) - fma(br, br, bi * bi));
+  } else {
+    const double ar = vr[0], ai = vi[0], br = vr[1], bi = vi[1], cr = vr[N - 1], ci = vi[N - 1];
+    // conj(a) b + conj(b) c, scaled by sqrt 2 (twice the 1/sqrt 2 couplings)
+    const double sr = fma(ar, br, ai * bi) + fma(br, cr, bi * ci);
+    const double si = fma(ar, bi, -ai * br) + fma(br, ci, -bi * cr);
+    jx = 2.0 * kRsqrt2 * sr;
+    jy = 2.0 * kRsqrt2 * si;
+    jz = fma(ar, ar, ai * ai) - fma(cr, cr, ci * ci);
+  }
+  j3[0] = jx;
+  j3[1] = jy;
+  j3[2] = jz;
+}
+
 // Product of the lane's (up to) E consecutive matrices, later on the left
 // (the identity for a lane past the end).  The first matrix is loaded as
 // the start value: multiplying it into the identity would give the same
@@ -44,12 +70,14 @@ __device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_
 
 // Tile apply: before[i] = M[i-1] ... M[tT] start for i in tile t (the state
 // entering element i); after_last (optional) receives M[n-1] ... applied
-// when the tile holds the last element.  Every lane must call this.
+// when the tile holds the last element; spin (optional, [n][3]) receives
+// <J_x>, <J_y>, <J_z> of every state written.  Every lane must call this.
 template <int N, int E>
 __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t n, int64_t tile,
                                            int lane, bool valid, const double* __restrict__ start,
                                            double* __restrict__ before,
-                                           double* __restrict__ after_last) {
+                                           double* __restrict__ after_last,
+                                           double* __restrict__ spin = nullptr) {
   const int64_t base = tile * (64 * E) + (int64_t)lane * E;
   Mat<N> P;
   lane_product<N, E>(M, n, base, P);
@@ -98,6 +126,7 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
         o[2 * a] = vr[a];
         o[2 * a + 1] = vi[a];
       }
+      if (spin) project_spin<N>(vr, vi, spin + 3 * idx);
       Mat<N> Y;
       load_mat<N>(M + (size_t)idx * 2 * N * N, Y);
       double wr_[N], wi_[N];

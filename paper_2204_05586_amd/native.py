@@ -33,7 +33,7 @@ EXPORTS = [
     "mss_adjoint_workspace_size", "mss_adjoint_param_count", "mss_adjoint_run",
     "mss_adjoint_plan_destroy", "mss_sampler_create", "mss_sampler_log", "mss_sampler_integrate",
     "mss_sampler_solve", "mss_sampler_destroy", "mss_batch_plan_create_sampled",
-    "mss_sampler_create_for_terms", "mss_sampler_min_params",
+    "mss_sampler_create_for_terms", "mss_sampler_min_params", "mss_propagate_spin",
 ]
 
 MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
@@ -123,6 +123,7 @@ def lib() -> C.CDLL:
         L.mss_propagate_workspace_size.argtypes = [C.c_int32, C.c_int64, C.POINTER(sz)]
         L.mss_integrate.argtypes = [PP, vp, vp, vp, C.POINTER(Launch), vp]
         L.mss_propagate.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_propagate_spin.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.mss_solve.argtypes = [PP, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.mss_spin_projection.argtypes = [C.c_int32, C.c_int64, vp, vp, vp]
         L.mss_spin_projection.restype = C.c_int
@@ -177,7 +178,8 @@ def lib() -> C.CDLL:
                      "mss_adjoint_plan_create", "mss_adjoint_workspace_size",
                      "mss_adjoint_param_count", "mss_adjoint_run", "mss_sampler_create",
                      "mss_sampler_integrate", "mss_sampler_solve",
-                     "mss_batch_plan_create_sampled"):
+                     "mss_batch_plan_create_sampled", "mss_sampler_create_for_terms",
+                     "mss_propagate_spin"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -299,11 +301,19 @@ def integrate(prob, params, U, time=None, launch: Optional[tuple[int, int]] = No
     check(lib().mss_integrate(pk.ref, _ptr(params), _ptr(U), _ptr(time), ln, _stream(stream)))
 
 
-def propagate(spin_twice: int, U, psi0, psi, psi_final=None, ws=None, stream=None) -> None:
+def propagate(spin_twice: int, U, psi0, psi, psi_final=None, ws=None, stream=None,
+              spin=None) -> None:
+    """mss_propagate; with a device tensor spin [K, 3] (float64),
+    mss_propagate_spin: <J_x>, <J_y>, <J_z> of every state in the same pass."""
     K = int(U.shape[0])
     nbytes = 0 if ws is None else int(ws.numel() * ws.element_size())
-    check(lib().mss_propagate(int(spin_twice), K, _ptr(U), _ptr(psi0), _ptr(psi),
-                              _ptr(psi_final), _ptr(ws), nbytes, _stream(stream)))
+    if spin is None:
+        check(lib().mss_propagate(int(spin_twice), K, _ptr(U), _ptr(psi0), _ptr(psi),
+                                  _ptr(psi_final), _ptr(ws), nbytes, _stream(stream)))
+    else:
+        check(lib().mss_propagate_spin(int(spin_twice), K, _ptr(U), _ptr(psi0), _ptr(psi),
+                                       _ptr(psi_final), _ptr(spin), _ptr(ws), nbytes,
+                                       _stream(stream)))
 
 
 def solve_into(prob, params, psi0, psi, psi_final=None, U=None, time=None, ws=None,
@@ -325,10 +335,11 @@ def spin_projection(psi, stream=None):
 
 
 def solve(prob, store_u: bool = False, want_time: bool = False, device="cuda",
-          stream=None, sampler: "Optional[Sampler]" = None) -> dict:
+          stream=None, sampler: "Optional[Sampler]" = None, want_spin: bool = False) -> dict:
     """Allocate outputs on the device and run the whole path (mss_solve, or
-    mss_sampler_solve when a sampler supplies the field).  Returns torch
-    tensors: psi [K, N], psi_final [N], U [K, N, N] or None, time [K] or None."""
+    mss_sampler_solve when a sampler supplies the field; with want_spin the
+    integrator then mss_propagate_spin).  Returns torch tensors: psi [K, N],
+    psi_final [N], U [K, N, N] or None, time [K] or None, spin [K, 3] or None."""
     import torch
     K, N = int(prob.n_samples), int(prob.spin_twice) + 1
     params = device_params(prob, device)
@@ -337,12 +348,22 @@ def solve(prob, store_u: bool = False, want_time: bool = False, device="cuda",
     fin = torch.empty((N,), dtype=torch.complex128, device=device)
     U = torch.empty((K, N, N), dtype=torch.complex128, device=device) if store_u else None
     time = torch.empty((K,), dtype=torch.float64, device=device) if want_time else None
+    if want_spin:
+        Uw = U if U is not None else torch.empty((K, N, N), dtype=torch.complex128, device=device)
+        if sampler is None:
+            integrate(prob, params, Uw, time, stream=stream)
+        else:
+            sampler.integrate(prob, params, Uw, time, stream=stream)
+        spin = torch.empty((K, 3), dtype=torch.float64, device=device)
+        ws = alloc_workspace(propagate_workspace_size(prob.spin_twice, K), device)
+        propagate(prob.spin_twice, Uw, psi0, psi, fin, ws, stream, spin=spin)
+        return {"psi": psi, "psi_final": fin, "U": U, "time": time, "spin": spin}
     ws = alloc_workspace(workspace_size(prob, store_u), device)
     if sampler is None:
         solve_into(prob, params, psi0, psi, fin, U, time, ws, stream)
     else:
         sampler.solve_into(prob, params, psi0, psi, fin, U, time, ws, stream)
-    return {"psi": psi, "psi_final": fin, "U": U, "time": time}
+    return {"psi": psi, "psi_final": fin, "U": U, "time": time, "spin": None}
 
 
 # ---- user field samplers ---------------------------------------------------

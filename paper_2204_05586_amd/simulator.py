@@ -102,11 +102,14 @@ class Simulator:
 
     def evaluate(self, psi0, t_start: float, t_end: float, dt_integration: float,
                  dt_output: float, params=None, keep_operators: bool = True,
-                 stream=None) -> Results:
+                 stream=None, want_spin: bool = False) -> Results:
+        """One simulation.  want_spin: also form <J> of every state in the
+        last pass of the state product (``Results.spin`` ready, no second
+        read of the states)."""
         prob = self.problem(t_start, t_end, dt_integration, dt_output, params, psi0)
         native.validate(prob)
         if self.sampler is not None:
             prob = prob.replace(terms=[])
         r = native.solve(prob, store_u=keep_operators, want_time=True, device=self.device,
-                         stream=stream, sampler=self.sampler)
-        return Results(r["time"], r["psi"], r["U"], r["psi_final"])
+                         stream=stream, sampler=self.sampler, want_spin=want_spin)
+        return Results(r["time"], r["psi"], r["U"], r["psi_final"], r["spin"])

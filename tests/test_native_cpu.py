@@ -101,6 +101,15 @@ def test_solve_requires_buffers():
     assert "psi0" in native.last_error()
 
 
+def test_propagate_spin_requires_output():
+    L = native.lib()
+    buf = (C.c_double * 64)()
+    st = L.mss_propagate_spin(1, 4, buf, buf, buf, None, None, None, 0, None)
+    assert st == native.MSS_E_INVALID and "spin" in native.last_error()
+    st = L.mss_propagate_spin(3, 4, buf, buf, buf, None, buf, None, 0, None)
+    assert st == native.MSS_E_INVALID and "spin_twice" in native.last_error()
+
+
 # ---- user field samplers (compiled at run time; needs no GPU) ---------------
 
 def test_sampler_compiles_without_gpu():
