@@ -38,9 +38,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # sources are unchanged.
 MEASURED_TRAFFIC = {
     ("mss_user_work_integrate", "batched_sensing"): {
-        "src": "1cc4790fc03a6c44",
-        "fetch_kib": 4549.125, "write_kib": 64034595.375,
-        "bytes": int(round((4549.125 * 2.000 + 64034595.375 * 1.000) * 1024)),
+        "src": "1ebb13ca9534dbd1",
+        "fetch_kib": 4554.9375, "write_kib": 64034410.71875,
+        "bytes": int(round((4554.9375 * 2.000 + 64034410.71875 * 1.000) * 1024)),
     },
 }
 
@@ -366,17 +366,18 @@ def bench_next_rows(reps: int = 20) -> dict:
     U = torch.empty((K, N, N), dtype=torch.complex128, device="cuda")
 
     def timed(fn) -> float:
+        # back-to-back launches between one pair of events: the per-launch
+        # time of short kernels without an event pair's own overhead
         for _ in range(3):
             fn()
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(reps)]
-        for a, b in evs:
-            a.record(stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
             fn()
-            b.record(stream)
+        b.record(stream)
         torch.cuda.synchronize()
-        return statistics.mean(a.elapsed_time(b) for a, b in evs)
+        return a.elapsed_time(b) / reps
 
     def alu(flops_per_step: int, ms: float) -> dict:
         tf = flops_per_step * fine / (ms * 1e-3) / 1e12
