@@ -84,10 +84,38 @@ def cpu_baseline(problems, seconds: float) -> dict:
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
+    # one thread, on the same simulations in the same order, for a third of the time
+    oracle.set_threads(1)
+    one_steps, one_used, t1 = 0, 0, time.perf_counter()
+    try:
+        for p in problems:
+            oracle.solve(p)
+            one_steps += p.fine_steps
+            one_used += 1
+            if time.perf_counter() - t1 >= seconds / 3:
+                break
+    finally:
+        oracle.set_threads(threads)
+    dt1 = time.perf_counter() - t1
     return {"value": round(done_steps / dt, 1), "unit": "fine_steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{used} of {len(problems)} simulations ({done_steps} fine steps, "
-                      f"{dt:.1f} s, {threads} OpenMP threads over intervals)"}
+                      f"{dt:.1f} s, {threads} OpenMP threads over intervals)",
+            "single_thread": {"value": round(one_steps / dt1, 1),
+                              "sample": f"{one_used} simulations ({one_steps} fine steps, "
+                                        f"{dt1:.1f} s)"},
+            "host": {"cpu_count": os.cpu_count(), "model": _cpu_model()}}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_plain(prob, steps: int, warmup: int, specialise: bool = True) -> dict:

@@ -45,3 +45,34 @@ def test_spin_length_conserved(oracle):
     p3 = p2.replace(spin_twice=2, psi0=SA.d1_state(p2.psi0))
     J = oracle.spin_projection(oracle.solve(p3)["psi"])
     assert np.max(np.abs(np.linalg.norm(J, axis=1) - 1.0)) < 1e-12
+
+
+def _rot(axis, a):
+    c, s = math.cos(a), math.sin(a)
+    if axis == "x":
+        return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+
+
+@pytest.mark.parametrize("spin_twice", [1, 2])
+def test_circular_drive_closed_form(oracle, spin_twice):
+    """Resonant circular drive f_x + i f_y = A e^{i w0 t}, f_z = F0, w0 = 2 pi F0:
+    in the frame rotating at w0 about z the Hamiltonian is the constant
+    2 pi A J_x, so <J>(t) = R_z(w0 t) R_x(2 pi A t) <J>(0) (right-handed
+    rotations of the vector).  With the rotating frame on, each interval's
+    frame Hamiltonian is constant and the method is exact to rounding."""
+    F0, A = 2.0e4, 900.0
+    T = W.Term
+    terms = [T(W.COS, W.X, a=A, f=F0), T(W.SIN, W.Y, a=A, f=F0), T(W.CONST, W.Z, a=F0)]
+    th, ph = 1.1, 0.4
+    half = np.array([math.cos(th / 2), np.exp(1j * ph) * math.sin(th / 2)])
+    psi0 = half if spin_twice == 1 else SA.d1_state(half[None])[0]
+    p = W.Problem(spin_twice, terms, 0.0, 3e-6, 500, 6, 28, True, psi0=psi0)
+    J = oracle.spin_projection(oracle.solve(p)["psi"])
+    s = spin_twice / 2
+    v0 = s * np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    assert np.max(np.abs(J[0] - v0)) < 1e-15
+    for k in (1, 77, 250, 499):
+        t = k * 3e-6
+        ref = _rot("z", 2 * math.pi * F0 * t) @ _rot("x", 2 * math.pi * A * t) @ v0
+        assert np.max(np.abs(J[k] - ref)) < 2e-12, (k, J[k], ref)
