@@ -293,10 +293,15 @@ def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib:
         th.start()
         base = srv.clock() + 0.05
         for r in stream:
-            delay = base + r.arrival - srv.clock()
-            if delay > 0:
-                time.sleep(delay)
-            q.put((srv.submit(r.problem), base + r.arrival, r.problem.fine_steps))
+            # sleep to within 2 ms of the arrival, then spin on the server
+            # clock: the load generator's own lateness stays out of the latency
+            due = base + r.arrival
+            delay = due - srv.clock()
+            if delay > 0.002:
+                time.sleep(delay - 0.002)
+            while srv.clock() < due:
+                pass
+            q.put((srv.submit(r.problem), due, r.problem.fine_steps))
         q.put(None)
         th.join()
         lat = np.array([d - a for a, _, d, _ in records]) * 1e3

@@ -371,7 +371,7 @@ void mss_batch_plan_destroy(mss_batch_plan* plan);
 /* ---- serving ------------------------------------------------------------
  * Continuous batching of simulation requests (mixed spin and length) on the
  * current device.  Requests are admitted in arrival order while their
- * device block (K (N^2 + N) 16 bytes plus small state, parameter and scan
+ * device block (K (N^2 + N) 16 bytes plus a small final-state and scan
  * arrays) fits in the HBM budget and an active slot is free; otherwise they
  * wait (back-pressure).  A scheduler thread runs rounds: every active
  * request gets a share of the round's work, all shares are integrated in
@@ -384,7 +384,9 @@ typedef struct mss_server mss_server;
 typedef struct mss_server_options {
   size_t hbm_budget;      /* bytes of device memory for requests (0: 80 % of free memory) */
   int32_t max_active;     /* requests admitted at once (0: 512) */
-  int32_t slices;         /* lanes per interval, power of two <= 64 (0: 1) */
+  int32_t slices;         /* lanes per interval, power of two <= 64, capped at each request's
+                             n_fine; 0: per request, the least 2^s (s <= log2 n_fine) with
+                             n_samples 2^s >= the device's resident lanes (CUs x 512) */
   double iteration_steps; /* spin-1 fine steps per round (spin-1/2 steps weigh 1/16; 0: 3e7) */
 } mss_server_options;
 
@@ -434,6 +436,13 @@ mss_status mss_server_copy_out(mss_server* server, uint64_t ticket, double* psi,
 mss_status mss_server_release(mss_server* server, uint64_t ticket);
 
 mss_status mss_server_stats_get(mss_server* server, mss_server_stats* out);
+
+/* Lanes per interval the server gives a problem (options.slices, or its
+ * per-request choice): a served request's operators and states are bit for
+ * bit those of mss_integrate with launch {slices, block} followed by
+ * mss_propagate.  problem: host, validated as by mss_validate. */
+mss_status mss_server_request_slices(const mss_server* server, const mss_problem* problem,
+                                     int32_t* slices);
 
 /* Seconds since the server was created (the clock of the request times). */
 double mss_server_clock(const mss_server* server);

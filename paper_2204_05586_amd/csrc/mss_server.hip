@@ -2,15 +2,21 @@
 // requests of mixed spin and length on one GPU.
 //
 //  * Memory: one device pool of the HBM budget, carved first-fit into one
-//    block per admitted request (parameters, initial / final state,
-//    operators, states, scan scratch).  A request is admitted (FIFO) only
-//    when its block fits and an active slot is free; otherwise it waits in
-//    the queue (back-pressure).  Blocks return to the pool on release.
+//    block per admitted request (final state, operators, states, scan
+//    scratch).  A request is admitted (FIFO) only when its block fits and
+//    an active slot is free; otherwise it waits in the queue
+//    (back-pressure).  Blocks return to the pool on release.  Parameters
+//    and initial states travel with each round's descriptors (one pinned
+//    upload per round).
 //  * Scheduling: a host thread runs rounds.  Each round gives every active
 //    request with intervals left a share of the round's work budget (whole
 //    64-interval items), integrates all those interval ranges in one
 //    persistent-integrator launch, and scans the requests whose last range
-//    is in the round.  Requests that arrive meanwhile join the next round,
+//    is in the round.  A request's intervals are split over 2^s lanes each,
+//    s fixed per request (by default the least s for which its intervals
+//    times 2^s fill the device's resident lanes, at most its fine steps), so
+//    a short request alone is not held up by one lane's serial steps and
+//    its results never depend on the other requests.  Requests that arrive meanwhile join the next round,
 //    so work of different requests overlaps on the device.  Two rounds are
 //    kept in flight (descriptor buffers are double-buffered behind events).
 //  * Results stay in the request's device block until release.
@@ -89,18 +95,17 @@ struct Request {
   std::vector<mss_term> terms;
   std::vector<double> params, psi0;
   int N = 0;
+  int slices_log2 = 0;
   size_t bytes = 0, off = 0;
-  double *d_params = nullptr, *d_psi0 = nullptr, *d_fin = nullptr, *d_U = nullptr,
-         *d_psi = nullptr, *d_scan = nullptr;
+  double *d_fin = nullptr, *d_U = nullptr, *d_psi = nullptr, *d_scan = nullptr;
   int64_t next_k = 0;
   int32_t state = MSS_REQ_QUEUED;
-  bool uploaded = false;
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
 size_t request_bytes(const mss_problem& p) {
   const int N = p.spin_twice + 1;
-  size_t b = a256((size_t)std::max(1, p.n_params) * 8) + a256((size_t)N * 16) * 2;
+  size_t b = a256((size_t)N * 16);
   b += a256((size_t)p.n_samples * N * N * 16) + a256((size_t)p.n_samples * N * 16);
   b += scan_scratch_bytes(N, p.n_samples);
   return b;
@@ -120,14 +125,16 @@ struct mss_server {
   Pool pool;
   size_t peak = 0;
   hipStream_t stream = nullptr;
-  // per round slot: device descriptors, pinned staging, completion event
+  // per round slot: device descriptors (+ the queue counter after them),
+  // pinned staging of the same capacity, completion event
   static constexpr int kSlots = 2;
   void* desc[kSlots] = {};
   char* staging[kSlots] = {};
-  size_t desc_bytes = 0;
+  size_t cap[kSlots] = {};
   hipEvent_t done[kSlots] = {};
   unsigned long long* counter[kSlots] = {};
   int grid_cap = 0;
+  int64_t lanes = 0;  // resident lanes of the device: CUs x 4 SIMDs x 2 waves x 64
   std::chrono::steady_clock::time_point t0;
 
   std::mutex mu;
@@ -146,7 +153,34 @@ struct mss_server {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   void run();
+  hipError_t ensure_slot(int slot, size_t bytes);
+  int request_slices_log2(const mss_problem& p) const;
 };
+
+// Grow a slot's buffers to at least bytes (the slot must be idle).
+hipError_t mss_server::ensure_slot(int slot, size_t bytes) {
+  if (bytes <= cap[slot]) return hipSuccess;
+  const size_t want = std::max(a256(bytes), 2 * cap[slot]);
+  if (desc[slot]) (void)hipFree(desc[slot]);
+  if (staging[slot]) (void)hipHostFree(staging[slot]);
+  desc[slot] = nullptr;
+  staging[slot] = nullptr;
+  cap[slot] = 0;
+  hipError_t e = hipMalloc(&desc[slot], want + 256);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&staging[slot], want);
+  if (e != hipSuccess) return e;
+  cap[slot] = want;
+  counter[slot] = (unsigned long long*)((char*)desc[slot] + want);
+  return hipSuccess;
+}
+
+int mss_server::request_slices_log2(const mss_problem& p) const {
+  const int top = api_ilog2(std::min(64, p.n_fine));
+  if (opt.slices > 0) return std::min(api_ilog2(opt.slices), top);
+  int s = 0;
+  while (s < top && (p.n_samples << s) < lanes) ++s;
+  return s;
+}
 
 namespace {
 
@@ -165,7 +199,7 @@ void mss_server::run() {
   std::deque<Inflight> inflight;
   int round = 0;
   for (;;) {
-    std::vector<Request*> admitted, work;
+    std::vector<Request*> work;
     {
       std::unique_lock<std::mutex> lock(mu);
       for (;;) {
@@ -180,10 +214,6 @@ void mss_server::run() {
           char* b = pool_base + off;
           const int N = r->N;
           const int64_t K = r->prob.n_samples;
-          r->d_params = (double*)b;
-          b += a256((size_t)std::max(1, r->prob.n_params) * 8);
-          r->d_psi0 = (double*)b;
-          b += a256((size_t)N * 16);
           r->d_fin = (double*)b;
           b += a256((size_t)N * 16);
           r->d_U = (double*)b;
@@ -195,7 +225,6 @@ void mss_server::run() {
           r->t_admit = now();
           queue.pop_front();
           active.push_back(r->ticket);
-          admitted.push_back(r);
         }
         for (uint64_t t : active) {
           Request* r = reqs[t].get();
@@ -207,16 +236,7 @@ void mss_server::run() {
       if (stop && work.empty() && inflight.empty()) break;
     }
     hipError_t e = hipSuccess;
-    // uploads of newly admitted requests (their host copies live until release)
-    for (Request* r : admitted) {
-      if (r->prob.n_params > 0 && e == hipSuccess)
-        e = hipMemcpyAsync(r->d_params, r->params.data(), r->params.size() * 8,
-                           hipMemcpyHostToDevice, stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(r->d_psi0, r->psi0.data(), r->psi0.size() * 8, hipMemcpyHostToDevice,
-                           stream);
-    }
-    if (!work.empty() && e == hipSuccess) {
+    if (!work.empty()) {
       const int slot = round % kSlots;
       if (inflight.size() >= (size_t)kSlots) {
         // the slot's previous round must be complete before its buffers are reused
@@ -234,17 +254,15 @@ void mss_server::run() {
       double round_steps = 0;
       for (Request* r : work) {
         const double w = (r->N == 3 ? 1.0 : 1.0 / 16.0) * r->prob.n_fine;
-        const int per = 64 >> api_ilog2(std::min(opt.slices, r->prob.n_fine));
+        const int per = 64 >> r->slices_log2;
         int64_t k = (int64_t)(share / w);
         k = std::max<int64_t>(per, k / per * per);
         k = std::min<int64_t>(k, r->prob.n_samples - r->next_k);
         const bool last = r->next_k + k == r->prob.n_samples;
         mss_problem q = r->prob;
         q.terms = r->terms.data();
-        ws.add(q, api_ilog2(std::min(opt.slices, r->prob.n_fine)), r->next_k, k, last);
+        ws.add(q, r->slices_log2, r->next_k, k, last);
         SimDesc& d = ws.sims.back();
-        d.params = r->prob.n_params > 0 ? r->d_params : nullptr;
-        d.psi0 = r->d_psi0;
         d.psi = r->d_psi;
         d.psi_final = r->d_fin;
         d.U = r->d_U;
@@ -254,14 +272,32 @@ void mss_server::run() {
         if (last) inf.finishing.push_back(r->ticket);
       }
       ws.finalize();
+      // the image: descriptors, then every range's parameters and initial state
+      const size_t base = a256(ws.packed_bytes());
+      size_t total = base;
+      std::vector<size_t> o_par(work.size()), o_psi0(work.size());
+      for (size_t i = 0; i < work.size(); ++i) {
+        o_par[i] = total;
+        total += a256((size_t)std::max(1, work[i]->prob.n_params) * 8);
+        o_psi0[i] = total;
+        total += a256((size_t)work[i]->N * 16);
+      }
+      e = ensure_slot(slot, total);
       size_t o_sims, o_terms;
       std::vector<size_t> o_red, o_app;
-      if (ws.packed_bytes() > desc_bytes) {
-        e = hipErrorOutOfMemory;
-      } else if (e == hipSuccess) {
+      if (e == hipSuccess) {
+        char* dev = (char*)desc[slot];
+        for (size_t i = 0; i < work.size(); ++i) {
+          const Request* r = work[i];
+          SimDesc& d = ws.sims[i];
+          d.params = r->prob.n_params > 0 ? (const double*)(dev + o_par[i]) : nullptr;
+          d.psi0 = (const double*)(dev + o_psi0[i]);
+          if (r->prob.n_params > 0)
+            memcpy(staging[slot] + o_par[i], r->params.data(), r->params.size() * 8);
+          memcpy(staging[slot] + o_psi0[i], r->psi0.data(), r->psi0.size() * 8);
+        }
         ws.pack(staging[slot], &o_sims, &o_terms, &o_red, &o_app);
-        e = hipMemcpyAsync(desc[slot], staging[slot], ws.packed_bytes(), hipMemcpyHostToDevice,
-                           stream);
+        e = hipMemcpyAsync(desc[slot], staging[slot], total, hipMemcpyHostToDevice, stream);
       }
       if (e == hipSuccess) {
         DevWork dw = device_view(ws, (const char*)desc[slot], o_sims, o_terms, o_red, o_app);
@@ -357,7 +393,6 @@ mss_status mss_server_create(const mss_server_options* options, mss_server** out
       (opt.slices & (opt.slices - 1)) != 0 || !(opt.iteration_steps >= 0.0))
     return api_fail(MSS_E_INVALID, "bad server options");
   if (!opt.max_active) opt.max_active = 512;
-  if (!opt.slices) opt.slices = 1;
   if (opt.iteration_steps == 0.0) opt.iteration_steps = 3e7;
   mss_server* S = new (std::nothrow) mss_server();
   if (!S) return api_fail(MSS_E_NOMEM, "host allocation failed");
@@ -385,23 +420,24 @@ mss_status mss_server_create(const mss_server_options* options, mss_server** out
     return api_hip_fail(e, "hipMalloc");
   }
   S->pool.reset(opt.hbm_budget);
-  // descriptor capacity for max_active requests of up to MSS_MAX_TERMS terms and 8 scan levels
-  WorkSet probe;
-  S->desc_bytes = a256((size_t)opt.max_active * sizeof(SimDesc)) +
-                  a256((size_t)opt.max_active * MSS_MAX_TERMS * sizeof(mss_term)) +
-                  17 * a256(((size_t)opt.max_active + 1) * 8) + 4096;
+  // initial slot capacity: descriptors of max_active requests of up to
+  // MSS_MAX_TERMS terms and 8 scan levels, and a spin-1 initial state and
+  // 32 parameters each (a slot grows when a round needs more)
+  const size_t slot_bytes = a256((size_t)opt.max_active * sizeof(SimDesc)) +
+                            a256((size_t)opt.max_active * MSS_MAX_TERMS * sizeof(mss_term)) +
+                            17 * a256(((size_t)opt.max_active + 1) * 8) +
+                            (size_t)opt.max_active * (a256(48) + a256(32 * 8)) + 4096;
   e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
   for (int i = 0; i < mss_server::kSlots && e == hipSuccess; ++i) {
-    e = hipMalloc(&S->desc[i], S->desc_bytes + 256);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&S->staging[i], S->desc_bytes);
+    e = S->ensure_slot(i, slot_bytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->done[i], hipEventDisableTiming);
-    if (e == hipSuccess) S->counter[i] = (unsigned long long*)((char*)S->desc[i] + S->desc_bytes);
   }
   if (e != hipSuccess) {
     destroy(S);
     return api_hip_fail(e, "server setup");
   }
   S->grid_cap = api_device_cu_count() * 2;
+  S->lanes = (int64_t)api_device_cu_count() * 4 * 2 * 64;
   S->worker = std::thread([S] { S->run(); });
   *out = S;
   return api_ok();
@@ -423,6 +459,7 @@ mss_status mss_server_submit(mss_server* S, const mss_problem* p, const double* 
   r->N = p->spin_twice + 1;
   r->psi0.assign(psi0, psi0 + 2 * r->N);
   r->bytes = request_bytes(*p);
+  r->slices_log2 = S->request_slices_log2(*p);
   if (r->bytes > S->opt.hbm_budget)
     return api_fail(MSS_E_NOMEM, "request needs %zu bytes, the budget is %zu", r->bytes,
                     S->opt.hbm_budget);
@@ -524,6 +561,15 @@ mss_status mss_server_stats_get(mss_server* S, mss_server_stats* out) {
   out->bytes_in_use = S->pool.used();
   out->bytes_peak = S->peak;
   out->budget = S->opt.hbm_budget;
+  return api_ok();
+}
+
+mss_status mss_server_request_slices(const mss_server* S, const mss_problem* p,
+                                     int32_t* slices) {
+  if (!S || !slices) return api_fail(MSS_E_INVALID, "server and slices are required");
+  mss_status s = api_validate_problem(p);
+  if (s != MSS_OK) return s;
+  *slices = 1 << S->request_slices_log2(*p);
   return api_ok();
 }
 

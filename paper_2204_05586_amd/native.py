@@ -29,7 +29,8 @@ EXPORTS = [
     "mss_batch_info", "mss_batch_run", "mss_batch_integrate", "mss_batch_propagate",
     "mss_batch_plan_destroy", "mss_server_create", "mss_server_submit", "mss_server_poll",
     "mss_server_wait", "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
-    "mss_server_clock", "mss_server_destroy", "mss_adjoint_plan_create",
+    "mss_server_clock", "mss_server_destroy", "mss_server_request_slices",
+    "mss_adjoint_plan_create",
     "mss_adjoint_workspace_size", "mss_adjoint_param_count", "mss_adjoint_run",
     "mss_adjoint_plan_destroy", "mss_sampler_create", "mss_sampler_log", "mss_sampler_integrate",
     "mss_sampler_solve", "mss_sampler_destroy", "mss_batch_plan_create_sampled",
@@ -145,6 +146,7 @@ def lib() -> C.CDLL:
         L.mss_server_copy_out.argtypes = [vp, C.c_uint64, vp, vp, vp, vp]
         L.mss_server_release.argtypes = [vp, C.c_uint64]
         L.mss_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+        L.mss_server_request_slices.argtypes = [vp, PP, C.POINTER(C.c_int32)]
         L.mss_server_clock.argtypes = [vp]
         L.mss_server_clock.restype = C.c_double
         L.mss_server_destroy.argtypes = [vp]
@@ -179,7 +181,7 @@ def lib() -> C.CDLL:
                      "mss_adjoint_param_count", "mss_adjoint_run", "mss_sampler_create",
                      "mss_sampler_integrate", "mss_sampler_solve",
                      "mss_batch_plan_create_sampled", "mss_sampler_create_for_terms",
-                     "mss_propagate_spin"):
+                     "mss_propagate_spin", "mss_server_request_slices"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -590,7 +592,9 @@ class BatchPlan:
 # ---- serving ---------------------------------------------------------------
 
 class Server:
-    """Continuous-batching simulation server (mss_server_*)."""
+    """Continuous-batching simulation server (mss_server_*).  slices: lanes
+    per interval; 0 lets the server choose per request from its length
+    (``request_slices``)."""
 
     def __init__(self, hbm_budget: int = 0, max_active: int = 0, slices: int = 0,
                  iteration_steps: float = 0.0):
@@ -602,6 +606,14 @@ class Server:
 
     def clock(self) -> float:
         return lib().mss_server_clock(self.handle)
+
+    def request_slices(self, prob) -> int:
+        """Lanes per interval the server gives this problem: its results are
+        those of ``integrate(..., launch=(slices, 256))`` and ``propagate``."""
+        pk = PackedProblem(prob)
+        out = C.c_int32()
+        check(lib().mss_server_request_slices(self.handle, pk.ref, C.byref(out)))
+        return out.value
 
     def submit(self, prob) -> int:
         pk = PackedProblem(prob)

@@ -21,9 +21,9 @@ def torch_dev():
     return torch
 
 
-def _alone(p):
-    """The single-simulation path with one lane per interval (the server's
-    lane mapping)."""
+def _alone(p, slices=1):
+    """The single-simulation path with the server's lane mapping (slices
+    lanes per interval)."""
     import torch
     from paper_2204_05586_amd import native
     K, N = p.n_samples, p.dim
@@ -31,7 +31,7 @@ def _alone(p):
     psi = torch.empty((K, N), dtype=torch.complex128, device="cuda")
     fin = torch.empty((N,), dtype=torch.complex128, device="cuda")
     ws = native.alloc_workspace(native.propagate_workspace_size(p.spin_twice, K))
-    native.integrate(p, native.device_params(p), U, launch=(1, 256))
+    native.integrate(p, native.device_params(p), U, launch=(slices, 256))
     native.propagate(p.spin_twice, U, native.device_state(p.psi0), psi, fin, ws)
     torch.cuda.synchronize()
     return psi, fin, U
@@ -44,34 +44,38 @@ def _mix(n, seed, k_hi=2e4):
 
 def test_server_results_equal_alone_and_oracle(torch_dev, oracle):
     """Requests split over several rounds (small round budget) give exactly
-    the operators and states of the same simulation run alone."""
+    the operators and states of the same simulation run alone with the lane
+    slicing the server chose for it (several requests here are short enough
+    to get more than one lane per interval)."""
     from paper_2204_05586_amd import native
     probs = _mix(40, seed=31)
     srv = native.Server(iteration_steps=2e5)
     print(f"[gpu] server mix of {len(probs)}", flush=True)
     tickets = [srv.submit(p) for p in probs]
-    worst, bitwise = 0.0, 0
+    worst, bitwise, n_sliced = 0.0, 0, 0
     for i, (t, p) in enumerate(zip(tickets, probs)):
         info = srv.wait(t, 120.0)
         assert info["state"] == native.MSS_REQ_DONE
         got = srv.fetch(t, p, want_u=True)
         import torch
         torch.cuda.synchronize()
-        psi, fin, U = _alone(p)
+        sl = srv.request_slices(p)
+        n_sliced += sl > 1
+        psi, fin, U = _alone(p, sl)
         d = max(float((got["psi"] - psi).abs().max()), float((got["U"] - U).abs().max()),
                 float((got["psi_final"] - fin).abs().max()))
         worst = max(worst, d)
         bitwise += d == 0.0
-        assert d <= 1e-13, (i, d)
+        assert d == 0.0, (i, sl, d)
         if i % 8 == 0:
             ref = oracle.solve(p)
             assert np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"])) <= TOL
             assert np.max(np.abs(got["psi_final"].cpu().numpy() - ref["psi_final"])) <= TOL
         srv.release(t)
     st = srv.stats()
-    print(f"served vs alone: max |d| = {worst:.3e}, bitwise {bitwise}/{len(probs)}, stats {st}",
-          flush=True)
-    assert st["rounds"] > 1 and st["completed"] == len(probs)
+    print(f"served vs alone: max |d| = {worst:.3e}, bitwise {bitwise}/{len(probs)}, "
+          f"{n_sliced} with more than one lane per interval, stats {st}", flush=True)
+    assert st["rounds"] > 1 and st["completed"] == len(probs) and n_sliced > 0
     srv.close()
 
 
@@ -118,6 +122,27 @@ def test_server_overlaps_requests(torch_dev):
     for t in tickets + [t_long]:
         srv.release(t)
     srv.close()
+
+
+def test_server_fixed_slices(torch_dev):
+    """options.slices fixes the lanes per interval (capped at a request's
+    fine steps) and the results follow it bit for bit."""
+    import torch
+    from paper_2204_05586_amd import native
+    probs = _mix(6, seed=33, k_hi=3e3)
+    for slices in (1, 4):
+        srv = native.Server(slices=slices, iteration_steps=1e5)
+        tickets = [srv.submit(p) for p in probs]
+        for t, p in zip(tickets, probs):
+            assert srv.request_slices(p) == min(slices, 1 << (int(p.n_fine).bit_length() - 1))
+            srv.wait(t, 120.0)
+            got = srv.fetch(t, p, want_u=True)
+            psi, fin, U = _alone(p, srv.request_slices(p))
+            torch.cuda.synchronize()
+            assert float((got["U"] - U).abs().max()) == 0.0
+            assert float((got["psi"] - psi).abs().max()) == 0.0
+            srv.release(t)
+        srv.close()
 
 
 def test_server_rejects_oversized(torch_dev):

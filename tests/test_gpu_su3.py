@@ -102,9 +102,9 @@ def test_su3_resonant_closed_form(dev, oracle):
         assert np.max(np.abs(g[k] - ref)) < 2e-12
 
 
-def _alone(p):
-    """The single-simulation path with one lane per interval (the lane
-    mapping of the batch plan below and of the server)."""
+def _alone(p, slices=1):
+    """The single-simulation path with slices lanes per interval (one: the
+    lane mapping of the batch plan below)."""
     import torch
     from paper_2204_05586_amd import native
     K, N = p.n_samples, p.dim
@@ -112,7 +112,7 @@ def _alone(p):
            "psi": torch.empty((K, N), dtype=torch.complex128, device="cuda"),
            "psi_final": torch.empty((N,), dtype=torch.complex128, device="cuda")}
     ws = native.alloc_workspace(native.propagate_workspace_size(p.spin_twice, K))
-    native.integrate(p, native.device_params(p), out["U"], launch=(1, 256))
+    native.integrate(p, native.device_params(p), out["U"], launch=(slices, 256))
     native.propagate(p.spin_twice, out["U"], native.device_state(p.psi0), out["psi"],
                      out["psi_final"], ws)
     torch.cuda.synchronize()
@@ -138,13 +138,14 @@ def test_su3_batch_and_server_equal_alone(dev, oracle):
     for i, p in enumerate(probs):
         got = plan.split(bufs, i)
         alone = _alone(p)
+        alone_srv = _alone(p, srv.request_slices(p))
         info = srv.wait(tickets[i], 60.0)
         assert info["state"] == native.MSS_REQ_DONE
         served = srv.fetch(tickets[i], p, want_u=True)
         torch.cuda.synchronize()
         for k in ("psi", "psi_final", "U"):
             assert float((got[k] - alone[k]).abs().max()) == 0.0, (i, k)
-            assert float((served[k] - alone[k]).abs().max()) == 0.0, (i, k)
+            assert float((served[k] - alone_srv[k]).abs().max()) == 0.0, (i, k)
         if i < 5:
             ref = oracle.solve(p, want_U=True)
             assert np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"])) <= TOL
