@@ -125,14 +125,13 @@ struct mss_server {
   Pool pool;
   size_t peak = 0;
   hipStream_t stream = nullptr;
-  // per round slot: device descriptors (+ the queue counter after them),
-  // pinned staging of the same capacity, completion event
+  // per round slot: device image, pinned staging of the same capacity,
+  // completion event
   static constexpr int kSlots = 2;
   void* desc[kSlots] = {};
   char* staging[kSlots] = {};
   size_t cap[kSlots] = {};
   hipEvent_t done[kSlots] = {};
-  unsigned long long* counter[kSlots] = {};
   int grid_cap = 0;
   int64_t lanes = 0;  // resident lanes of the device: CUs x 4 SIMDs x 2 waves x 64
   std::chrono::steady_clock::time_point t0;
@@ -166,11 +165,10 @@ hipError_t mss_server::ensure_slot(int slot, size_t bytes) {
   desc[slot] = nullptr;
   staging[slot] = nullptr;
   cap[slot] = 0;
-  hipError_t e = hipMalloc(&desc[slot], want + 256);
+  hipError_t e = hipMalloc(&desc[slot], want);
   if (e == hipSuccess) e = hipHostMalloc((void**)&staging[slot], want);
   if (e != hipSuccess) return e;
   cap[slot] = want;
-  counter[slot] = (unsigned long long*)((char*)desc[slot] + want);
   return hipSuccess;
 }
 
@@ -272,8 +270,9 @@ void mss_server::run() {
         if (last) inf.finishing.push_back(r->ticket);
       }
       ws.finalize();
-      // the image: descriptors, then every range's parameters and initial state
-      const size_t base = a256(ws.packed_bytes());
+      // the image: the work queue counter (uploaded as zero), descriptors,
+      // then every range's parameters and initial state
+      const size_t base = 256 + a256(ws.packed_bytes());
       size_t total = base;
       std::vector<size_t> o_par(work.size()), o_psi0(work.size());
       for (size_t i = 0; i < work.size(); ++i) {
@@ -296,13 +295,15 @@ void mss_server::run() {
             memcpy(staging[slot] + o_par[i], r->params.data(), r->params.size() * 8);
           memcpy(staging[slot] + o_psi0[i], r->psi0.data(), r->psi0.size() * 8);
         }
-        ws.pack(staging[slot], &o_sims, &o_terms, &o_red, &o_app);
+        memset(staging[slot], 0, 256);
+        ws.pack(staging[slot] + 256, &o_sims, &o_terms, &o_red, &o_app);
         e = hipMemcpyAsync(desc[slot], staging[slot], total, hipMemcpyHostToDevice, stream);
       }
       if (e == hipSuccess) {
-        DevWork dw = device_view(ws, (const char*)desc[slot], o_sims, o_terms, o_red, o_app);
+        DevWork dw = device_view(ws, (const char*)desc[slot] + 256, o_sims, o_terms, o_red, o_app);
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(grid_cap, (ws.n_items + 3) / 4));
-        e = launch_work_integrate(dw, counter[slot], blocks, stream);
+        e = launch_work_integrate(dw, (unsigned long long*)desc[slot], blocks, stream, nullptr,
+                                  true);
         if (e == hipSuccess) e = launch_work_scan(dw, stream);
         if (e == hipSuccess) e = hipEventRecord(done[slot], stream);
       }

@@ -64,12 +64,14 @@ struct DevWork {
 DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_t o_terms,
                     const std::vector<size_t>& o_reduce, const std::vector<size_t>& o_apply);
 
-// Enqueue the integrator (counter cleared by a kernel first) over every
-// range of the work set; grid_blocks 256-thread workgroups.  user_fn: the
-// work integrator of a user sampler's module (field from the sampler,
+// Enqueue the integrator (counter cleared by a kernel first, unless the
+// caller's stream has already zeroed it: counter_zeroed) over every range of
+// the work set; grid_blocks 256-thread workgroups.  user_fn: the work
+// integrator of a user sampler's module (field from the sampler,
 // descriptors carry no terms), or null for the field-program kernel.
 hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, int grid_blocks,
-                                 hipStream_t st, hipFunction_t user_fn = nullptr);
+                                 hipStream_t st, hipFunction_t user_fn = nullptr,
+                                 bool counter_zeroed = false);
 // Enqueue the scan of every scanning sequence (reduce up, apply down).
 hipError_t launch_work_scan(const DevWork& w, hipStream_t st);
 

@@ -257,9 +257,9 @@ DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_
 }
 
 hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, int grid_blocks,
-                                 hipStream_t st, hipFunction_t user_fn) {
+                                 hipStream_t st, hipFunction_t user_fn, bool counter_zeroed) {
   if (w.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(work_reset_kernel, dim3(1), dim3(64), 0, st, counter);
+  if (!counter_zeroed) hipLaunchKernelGGL(work_reset_kernel, dim3(1), dim3(64), 0, st, counter);
   IntegrateWorkArgs a{w.sims, w.terms, counter, w.n_items, w.n_sims};
   if (user_fn) {
     hipError_t e = hipGetLastError();

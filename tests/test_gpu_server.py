@@ -145,6 +145,35 @@ def test_server_fixed_slices(torch_dev):
         srv.close()
 
 
+def test_server_grows_round_image(torch_dev, oracle):
+    """Requests with 2048 parameters each (control instances with 1024
+    segments) on a server whose round image starts with room for 32 per
+    request (about 30 KB for 6 active requests, against 6 x 16 KB of
+    parameters here): the image grows and every result still equals the
+    request alone."""
+    import torch
+    from paper_2204_05586_amd import native
+    probs = W.control_batch(seed=9, n_inst=12, n_seg=1024, n_samples=200, n_fine=20)
+    assert all(len(p.params) == 2048 for p in probs)
+    srv = native.Server(max_active=6, iteration_steps=5e4)
+    tickets = [srv.submit(p) for p in probs]
+    print(f"[gpu] server with 512-parameter requests: {len(probs)}", flush=True)
+    for i, (t, p) in enumerate(zip(tickets, probs)):
+        info = srv.wait(t, 120.0)
+        assert info["state"] == native.MSS_REQ_DONE
+        got = srv.fetch(t, p, want_u=True)
+        psi, fin, U = _alone(p, srv.request_slices(p))
+        torch.cuda.synchronize()
+        assert float((got["U"] - U).abs().max()) == 0.0, i
+        assert float((got["psi"] - psi).abs().max()) == 0.0, i
+        if i == 0:
+            ref = oracle.solve(p)
+            assert np.max(np.abs(got["psi"].cpu().numpy() - ref["psi"])) <= TOL
+        srv.release(t)
+    assert srv.stats()["rounds"] > 1
+    srv.close()
+
+
 def test_server_rejects_oversized(torch_dev):
     from paper_2204_05586_amd import native
     srv = native.Server(hbm_budget=1 << 24)
