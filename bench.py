@@ -465,6 +465,69 @@ def bench_next_rows(reps: int = 20) -> dict:
     return out
 
 
+ACCURACY_FINE_STEPS = (1, 2, 5, 10, 20, 50, 100)  # fine steps per 0.5 us sample
+
+
+def accuracy_study(ref_fine: int = 500, reps: int = 3) -> dict:
+    """The paper's accuracy benchmark (Sec. "Evaluation of accuracy") on
+    the GPU: the 0.1 s sensing drive with its 1 ms pulse (2e5 samples of
+    0.5 us), spin-1 and spin-1/2, CF4, midpoint and Heun sampling with the
+    rotating frame on ("frame") and off ("lab"), over a range of fine steps.
+    Each point is [dt in ns, ms per simulation (integrator with the field
+    compiled in + scan, inputs resident, HIP events), error of eq. (error)
+    against CF4 with the frame at ref_fine fine steps per sample].  The
+    paper counts errors above 1e-3 as failures and floors its baseline at
+    1e-11."""
+    import numpy as np
+    import torch
+    from paper_2204_05586_amd import native, workloads as W
+    stream = torch.cuda.current_stream()
+    out = {"reference": f"CF4, rotating frame, {ref_fine} fine steps per sample"}
+    for spin_twice in (2, 1):
+        base = W.spin_one_sensing()
+        if spin_twice == 1:
+            base = base.replace(spin_twice=1, psi0=None,
+                                terms=[t for t in base.terms if t.comp != W.Q])
+        K, N = base.n_samples, base.dim
+        smp = native.Sampler.for_terms(base.terms)
+        params = native.device_params(base)
+        psi0 = native.device_state(base.psi0)
+        U = torch.empty((K, N, N), dtype=torch.complex128, device="cuda")
+        ws = native.alloc_workspace(native.propagate_workspace_size(spin_twice, K))
+
+        def run(prob, psi):
+            smp.integrate(prob.replace(terms=[]), params, U, stream=stream)
+            native.propagate(spin_twice, U, psi0, psi, None, ws, stream=stream)
+
+        ref = torch.empty((K, N), dtype=torch.complex128, device="cuda")
+        run(base.replace(n_fine=ref_fine), ref)
+        psi = torch.empty_like(ref)
+        series = {}
+        for mname, method in (("cf4", W.CF4), ("midpoint", W.MIDPOINT), ("heun", W.HEUN)):
+            for frame in (True, False):
+                pts = []
+                for L in ACCURACY_FINE_STEPS:
+                    p = base.replace(n_fine=L, method=method, rotating_frame=frame)
+                    run(p, psi)
+                    torch.cuda.synchronize()
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    for _ in range(reps):
+                        run(p, psi)
+                    b.record(stream)
+                    torch.cuda.synchronize()
+                    err = float(torch.sqrt((psi - ref).abs().square().sum())) / K
+                    pts.append([round(base.dt_out / L * 1e9, 3),
+                                round(a.elapsed_time(b) / reps, 4), float(f"{err:.3e}")])
+                series[f"{mname}_{'frame' if frame else 'lab'}"] = pts
+        out["spin_one" if spin_twice == 2 else "spin_half"] = series
+        smp.close()
+        del U, ws, ref, psi
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -577,6 +640,7 @@ def main():
     next_rows = None
     if not args.no_next_rows and args.plain_steps > 0:
         next_rows = bench_next_rows()
+        next_rows["f2_accuracy"] = accuracy_study()
 
     adjoint = None
     if args.adjoint_instances > 0:
