@@ -41,9 +41,21 @@ MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
 
 
 class MssError(RuntimeError):
+    """A non-OK status from the library; ``status`` holds the code.  Invalid
+    arguments also raise as ValueError and out-of-memory as MemoryError
+    (the subclasses below)."""
+
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
+
+
+class MssInvalidError(MssError, ValueError):
+    pass
+
+
+class MssNoMemoryError(MssError, MemoryError):
+    pass
 
 
 _STATUS_NAMES = {0: "MSS_OK", 1: "MSS_E_INVALID", 2: "MSS_E_NOMEM", 3: "MSS_E_DEVICE",
@@ -189,7 +201,8 @@ def lib() -> C.CDLL:
 
 def check(status: int) -> None:
     if status != MSS_OK:
-        raise MssError(status, lib().mss_last_error().decode())
+        cls = {MSS_E_INVALID: MssInvalidError, MSS_E_NOMEM: MssNoMemoryError}.get(status, MssError)
+        raise cls(status, lib().mss_last_error().decode())
 
 
 def last_error() -> str:

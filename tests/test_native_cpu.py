@@ -101,6 +101,18 @@ def test_solve_requires_buffers():
     assert "psi0" in native.last_error()
 
 
+def test_errors_raise_as_python_kinds():
+    """Invalid arguments raise ValueError, an impossible workspace
+    MemoryError, both still MssError with the status code."""
+    bad = W.spin_half_rabi(n_samples=4).replace(n_fine=0)
+    with pytest.raises(ValueError) as e:
+        native.check(native.lib().mss_validate(native.PackedProblem(bad).ref))
+    assert isinstance(e.value, native.MssError) and e.value.status == native.MSS_E_INVALID
+    with pytest.raises(MemoryError) as e:
+        native.check(native.MSS_E_NOMEM)
+    assert isinstance(e.value, native.MssError)
+
+
 def test_propagate_spin_requires_output():
     L = native.lib()
     buf = (C.c_double * 64)()
