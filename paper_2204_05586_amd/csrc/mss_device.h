@@ -535,81 +535,34 @@ __device__ __forceinline__ void cf4_angles(const Terms& fp, const double* __rest
   }
 }
 
-// Frame rotation at one node time per Euler-family step: cos and sin of
-// wr tau taken directly at the run's first node and advanced by the rotation
-// over one fine step (angle addition), as NodeRotations does for CF4.
-struct StepRotation {
-  double c, s;    // cos, sin of wr tau at the current node
-  double cd, sd;  // cos, sin of wr dt
-  __device__ __forceinline__ void start(double wr, double tau0, double dt) {
-#pragma clang fp contract(off)
-    sincos_cw(wr * tau0, &s, &c);
-    sincos_cw(wr * dt, &sd, &cd);
-  }
-  __device__ __forceinline__ void advance() {
-    const double cn = fma(c, cd, -s * sd);
-    const double sn = fma(s, cd, c * sd);
-    c = cn;
-    s = sn;
-  }
-};
-
-// 2 pi f at t_k + tau in the frame rotating at wr about z (rotation
-// cos / sin of wr tau; wr = 0: lab frame, c and s not read).
+// Angles of one Euler-family step (one exponential): H sampled at the
+// midpoint (method 1) or averaged over both ends of the step (method 2).
 template <class Terms>
-__device__ __forceinline__ void frame_node(const Terms& fp, const double* __restrict__ params,
-                                           double tk, double tau, double wr, double c, double s,
-                                           double w[4]) {
+__device__ __forceinline__ void euler_angles(const Terms& fp, const double* __restrict__ params,
+                                             double tk, int l, double dt, double wr, int method,
+                                             double th[4]) {
 #pragma clang fp contract(off)
-  double f[4];
-  field_eval(fp, params, tk + tau, f);
+  const int nn = method == 1 ? 1 : 2;
+  double w[2][4];
+  for (int i = 0; i < nn; ++i) {
+    const double c = method == 1 ? 0.5 : (i == 0 ? 0.0 : 1.0);
+    const double tau_i = ((double)l + c) * dt;
+    double f[4];
+    field_eval(fp, params, tk + tau_i, f);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) w[j] = kTwoPi * f[j];
-  if (wr != 0.0) {
-    // (w_x + i w_y) e^{-i wr tau}
-    const double xr = w[0] * c + w[1] * s;
-    const double xi = w[1] * c - w[0] * s;
-    w[0] = xr;
-    w[1] = xi;
-    w[2] = w[2] - wr;
-  }
-}
-
-// Euler-family steps l0 .. l1-1 (one exponential each) premultiplied into
-// U: H sampled at the step's midpoint (method 1), or averaged over its two
-// ends (method 2, Heun), where the end of one step is the start of the next
-// and is sampled once.
-template <int N, class Terms>
-__device__ __forceinline__ void euler_steps(const Terms& fp, const double* __restrict__ params,
-                                            double tk, int l0, int l1, double dt, double wr,
-                                            int tau, int method, Mat<N>& U) {
-  const double c0 = method == 1 ? 0.5 : 0.0;
-  StepRotation rot{1.0, 0.0, 1.0, 0.0};
-  if (wr != 0.0) rot.start(wr, ((double)l0 + c0) * dt, dt);
-  double wa[4];
-  if (method != 1) frame_node(fp, params, tk, (double)l0 * dt, wr, rot.c, rot.s, wa);
-  for (int l = l0; l < l1; ++l) {
-    double th[4];
-    if (method == 1) {
-      double w[4];
-      frame_node(fp, params, tk, ((double)l + 0.5) * dt, wr, rot.c, rot.s, w);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) th[j] = w[j] * dt;
-    } else {
-      if (wr != 0.0) rot.advance();  // to node l + 1
-      double wb[4];
-      frame_node(fp, params, tk, ((double)l + 1.0) * dt, wr, rot.c, rot.s, wb);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        th[j] = (wa[j] + wb[j]) / 2.0 * dt;
-        wa[j] = wb[j];
-      }
+    for (int j = 0; j < 4; ++j) w[i][j] = kTwoPi * f[j];
+    if (wr != 0.0) {
+      double s, cs;
+      sincos_cw(wr * tau_i, &s, &cs);
+      const double xr = w[i][0] * cs + w[i][1] * s;
+      const double xi = w[i][1] * cs - w[i][0] * s;
+      w[i][0] = xr;
+      w[i][1] = xi;
+      w[i][2] = w[i][2] - wr;
     }
-    if (method == 1 && wr != 0.0) rot.advance();
-    Mat<N> E;
-    Exponentiator<N>::apply(th, tau, E);
-    premultiply<N>(E, U);
   }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) th[j] = (method == 1 ? w[0][j] : (w[0][j] + w[1][j]) / 2.0) * dt;
 }
 
 // Start time of interval k and the frame rate omega_r = 2 pi f_z(t_k + Dt/2).
@@ -897,7 +850,13 @@ __device__ __forceinline__ void interval_operator(const Terms& terms, const doub
         premultiply<N>(E, U);
       }
     } else {
-      euler_steps<N>(terms, params, tk, l0, l1, dt, wr, tau, method, U);
+      for (int l = l0; l < l1; ++l) {
+        double th[4];
+        euler_angles(terms, params, tk, l, dt, wr, method, th);
+        Mat<N> E;
+        Exponentiator<N>::apply(th, tau, E);
+        premultiply<N>(E, U);
+      }
     }
   }
   for (int d = 1; d < (1 << sl); d <<= 1) {
