@@ -38,9 +38,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # sources are unchanged.
 MEASURED_TRAFFIC = {
     ("mss_user_work_integrate", "batched_sensing"): {
-        "src": "1ebb13ca9534dbd1",
-        "fetch_kib": 4554.9375, "write_kib": 64034410.71875,
-        "bytes": int(round((4554.9375 * 2.000 + 64034410.71875 * 1.000) * 1024)),
+        "src": "a400374b204b17d4",
+        "fetch_kib": 4502.25, "write_kib": 64034524.65625,
+        "bytes": int(round((4502.25 * 2.000 + 64034524.65625 * 1.000) * 1024)),
     },
 }
 
