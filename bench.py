@@ -576,6 +576,9 @@ def main():
         kernel = "mss_user_work_integrate" if res["specialized"] else "work_integrate_kernel"
         plain = (bench_plain(W.spin_one_sensing(), args.plain_steps, 3, not args.interpret)
                  if args.plain_steps > 0 else None)
+        # the spin-1/2 Rabi simulation (1e4 samples x 100 fine steps) the same way
+        plain_half = (bench_plain(W.spin_half_rabi(), args.plain_steps, 3, not args.interpret)
+                      if args.plain_steps > 0 else None)
         value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
             res["fine_steps"]
         config = {"workload": f"batched_sensing: {len(problems)} spin-1 simulations, seed 2, "
@@ -595,7 +598,10 @@ def main():
                  "graph_ms_per_step": round(res.get("graph_ms_per_step", 0.0), 3) or None,
                  "plain": ({k: (round(v, 4) if isinstance(v, float) else v)
                             for k, v in plain.items()} if plain else None),
-                 "batched_over_plain": round(value / plain["value"], 3) if plain else None}
+                 "batched_over_plain": round(value / plain["value"], 3) if plain else None,
+                 "plain_spin_half": ({k: (round(v, 4) if isinstance(v, float) else v)
+                                      for k, v in plain_half.items() if k != "tau"}
+                                     if plain_half else None)}
         base_problems = problems
     else:
         prob = W.spin_one_sensing() if args.workload == "spin_one_sensing" else W.spin_half_rabi()
