@@ -338,14 +338,17 @@ def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib:
     return out
 
 
-def bench_adjoint(n_inst: int, steps: int, warmup: int) -> dict:
+def bench_adjoint(n_inst: int, steps: int, warmup: int, specialise: bool = True) -> dict:
     """Gradients of the |0> population w.r.t. 512 piecewise-constant
     controls (256 amplitudes, 256 phases) for n_inst spin-1 instances of 1
-    ms (1e3 intervals x 100 CF4 steps, tau = 28, resonant rotating frame)."""
+    ms (1e3 intervals x 100 CF4 steps, tau = 28, resonant rotating frame).
+    The instances share one field program, compiled into the forward pass
+    unless specialise is off."""
     import torch
     from paper_2204_05586_amd import native, workloads as W
     probs = W.control_batch(seed=4, n_inst=n_inst)
-    plan = native.AdjointPlan(probs, 1)
+    plan = native.AdjointPlan(probs, 1, specialize=specialise)
+    forward = "field compiled in" if plan.specialized else "interpreted"
     bufs = plan.allocate()
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -360,7 +363,8 @@ def bench_adjoint(n_inst: int, steps: int, warmup: int) -> dict:
     plan.close()
     del bufs
     torch.cuda.empty_cache()
-    return {"instances": n_inst, "controls_per_instance": 512, "ms_per_gradient_batch": round(dt * 1e3, 3),
+    return {"instances": n_inst, "controls_per_instance": 512, "forward": forward,
+            "ms_per_gradient_batch": round(dt * 1e3, 3),
             "gradients_per_s": round(n_inst * 512 / dt, 1),
             "forward_plus_adjoint_fine_steps_per_s": round(fine / dt, 1)}
 
@@ -650,7 +654,7 @@ def main():
 
     adjoint = None
     if args.adjoint_instances > 0:
-        adjoint = bench_adjoint(args.adjoint_instances, 3, 1)
+        adjoint = bench_adjoint(args.adjoint_instances, 3, 1, not args.interpret)
 
     serving = None
     if args.serve_rates:

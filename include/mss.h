@@ -468,6 +468,15 @@ typedef struct mss_adjoint_plan mss_adjoint_plan;
  * packed layout of psi0 / psi_final is that of mss_batch_layout. */
 mss_status mss_adjoint_plan_create(int32_t n, const mss_problem* problems, const int64_t* param_off,
                                    int32_t level_m, mss_adjoint_plan** out);
+/* The same plan with the forward pass run by `forward`, a sampler that
+ * mss_sampler_create_for_terms made from the term list every problem
+ * carries (compared byte for byte; otherwise MSS_E_INVALID).  Its operators
+ * are bit for bit the interpreter's, so losses and gradients are those of
+ * mss_adjoint_plan_create; the backward pass still reads the terms.  The
+ * sampler stays owned by the caller and must outlive the plan. */
+mss_status mss_adjoint_plan_create_compiled(int32_t n, const mss_problem* problems,
+                                            const int64_t* param_off, int32_t level_m,
+                                            mss_sampler forward, mss_adjoint_plan** out);
 mss_status mss_adjoint_workspace_size(const mss_adjoint_plan* plan, size_t* bytes);
 /* Length of the gradient array: max over i of param_off[i] + n_params_i. */
 mss_status mss_adjoint_param_count(const mss_adjoint_plan* plan, int64_t* count);

@@ -65,14 +65,17 @@ class PopulationModel:
     vector concatenates the problems' parameter vectors in order;
     ``initial_params()`` returns it as a device tensor.
 
+    specialize: compile the problems' shared field program into the
+    forward pass (same losses and gradients, a faster forward).
+
     ``model(params)`` returns the [n] losses with gradient flowing to
     ``params`` (float64, on the device, length ``n_params``).  Everything
     runs on torch's current stream.  Calls reuse the model's buffers, so one
     model is not for concurrent use from several threads."""
 
-    def __init__(self, problems, level_m: int, device: str = "cuda"):
+    def __init__(self, problems, level_m: int, device: str = "cuda", specialize: bool = False):
         torch = _torch()
-        self.plan = native.AdjointPlan(problems, level_m)
+        self.plan = native.AdjointPlan(problems, level_m, specialize=specialize)
         self.bufs = self.plan.allocate(device)
         self.n_params = int(self.plan.n_grad)
         owner = np.zeros(max(1, self.n_params), dtype=np.int64)

@@ -565,6 +565,7 @@ struct mss_adjoint_plan {
   const void* bound[5] = {};
   bool have_bind = false;
   hipEvent_t last_run = nullptr;
+  mss_sampler forward = nullptr;  // the shared field compiled in, for the forward pass
 };
 
 namespace {
@@ -663,6 +664,23 @@ mss_status bind(mss_adjoint_plan* P, const double* params, const double* psi0, d
 }  // namespace
 
 extern "C" {
+
+mss_status mss_adjoint_plan_create_compiled(int32_t n, const mss_problem* problems,
+                                            const int64_t* param_off, int32_t level_m,
+                                            mss_sampler forward, mss_adjoint_plan** out) {
+  if (!out) return api_fail(MSS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!forward) return api_fail(MSS_E_INVALID, "forward sampler is NULL");
+  if (n < 1 || !problems) return api_fail(MSS_E_INVALID, "need at least one problem");
+  for (int i = 0; i < n; ++i)
+    if (!api_sampler_is_for_terms(forward, problems[i].terms, problems[i].n_terms))
+      return api_fail(MSS_E_INVALID,
+                      "simulation %d: the forward sampler was not generated from its terms", i);
+  mss_status s = mss_adjoint_plan_create(n, problems, param_off, level_m, out);
+  if (s != MSS_OK) return s;
+  (*out)->forward = forward;
+  return api_ok();
+}
 
 mss_status mss_adjoint_plan_create(int32_t n, const mss_problem* problems, const int64_t* param_off,
                                    int32_t level_m, mss_adjoint_plan** out) {
@@ -810,11 +828,13 @@ mss_status mss_adjoint_run(mss_adjoint_plan* P, const double* params, const doub
                     ws ? ws_bytes : (size_t)0);
   mss_status s = bind(P, params, psi0, grad, loss, ws);
   if (s != MSS_OK) return s;
+  hipFunction_t fwd_fn = nullptr;
+  if (P->forward && (s = api_sampler_work_function(P->forward, &fwd_fn)) != MSS_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   char* w = (char*)ws;
   const char* d = (const char*)P->desc;
   hipError_t e = launch_work_integrate(P->dfwd, (unsigned long long*)(w + P->o_counter),
-                                       P->grid_blocks, st);
+                                       P->grid_blocks, st, fwd_fn);
   if (e == hipSuccess) e = launch_work_scan(P->dfwd, st);
   if (e == hipSuccess) {
     SeedArgs sa{(const AdjDesc*)(d + P->a_sims), (const int64_t*)(d + P->a_psi0),

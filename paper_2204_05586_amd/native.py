@@ -35,6 +35,7 @@ EXPORTS = [
     "mss_adjoint_plan_destroy", "mss_sampler_create", "mss_sampler_log", "mss_sampler_integrate",
     "mss_sampler_solve", "mss_sampler_destroy", "mss_batch_plan_create_sampled",
     "mss_sampler_create_for_terms", "mss_sampler_min_params", "mss_propagate_spin",
+    "mss_adjoint_plan_create_compiled",
 ]
 
 MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
@@ -164,6 +165,8 @@ def lib() -> C.CDLL:
         L.mss_server_destroy.argtypes = [vp]
         L.mss_server_destroy.restype = None
         L.mss_adjoint_plan_create.argtypes = [C.c_int32, PP, i64p, C.c_int32, C.POINTER(vp)]
+        L.mss_adjoint_plan_create_compiled.argtypes = [C.c_int32, PP, i64p, C.c_int32, vp,
+                                                       C.POINTER(vp)]
         L.mss_adjoint_workspace_size.argtypes = [vp, C.POINTER(sz)]
         L.mss_adjoint_param_count.argtypes = [vp, i64p]
         L.mss_adjoint_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -193,7 +196,8 @@ def lib() -> C.CDLL:
                      "mss_adjoint_param_count", "mss_adjoint_run", "mss_sampler_create",
                      "mss_sampler_integrate", "mss_sampler_solve",
                      "mss_batch_plan_create_sampled", "mss_sampler_create_for_terms",
-                     "mss_propagate_spin", "mss_server_request_slices"):
+                     "mss_propagate_spin", "mss_server_request_slices",
+                     "mss_adjoint_plan_create_compiled"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -687,9 +691,13 @@ class Server:
 # ---- adjoint ---------------------------------------------------------------
 
 class AdjointPlan:
-    """Gradients of |psi_final[m]|^2 w.r.t. field parameters (mss_adjoint_*)."""
+    """Gradients of |psi_final[m]|^2 w.r.t. field parameters (mss_adjoint_*).
+    specialize: when every problem has the same term list, its field program
+    is compiled into the forward pass (mss_adjoint_plan_create_compiled; the
+    losses and gradients are bit for bit those without); ``specialized``
+    tells whether that happened.  The plan owns that sampler."""
 
-    def __init__(self, problems, level_m: int):
+    def __init__(self, problems, level_m: int, specialize: bool = False):
         self.problems = list(problems)
         n = len(self.problems)
         self.packed = [PackedProblem(p) for p in self.problems]
@@ -701,10 +709,18 @@ class AdjointPlan:
         self.param_off = np.zeros(max(1, n), dtype=np.int64)
         if n:
             self.param_off[:n] = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        self._sampler = None
+        sp = specialise(self.problems) if specialize else None
+        if sp is not None:
+            self._sampler = sp[0]
+        self.specialized = self._sampler is not None
         h = C.c_void_p()
-        check(lib().mss_adjoint_plan_create(
-            n, arr, self.param_off.ctypes.data_as(C.POINTER(C.c_int64)), int(level_m),
-            C.byref(h)))
+        offs = self.param_off.ctypes.data_as(C.POINTER(C.c_int64))
+        if self._sampler is None:
+            check(lib().mss_adjoint_plan_create(n, arr, offs, int(level_m), C.byref(h)))
+        else:
+            check(lib().mss_adjoint_plan_create_compiled(n, arr, offs, int(level_m),
+                                                         self._sampler._h, C.byref(h)))
         self.handle = h
         self.n = n
         cnt = C.c_int64()
@@ -741,6 +757,9 @@ class AdjointPlan:
         if getattr(self, "handle", None):
             lib().mss_adjoint_plan_destroy(self.handle)
             self.handle = None
+        if getattr(self, "_sampler", None) is not None:
+            self._sampler.close()
+            self._sampler = None
 
     def __del__(self):
         try:

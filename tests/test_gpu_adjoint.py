@@ -17,10 +17,11 @@ def torch_dev():
     return torch
 
 
-def _gpu_adjoint(probs, m):
+def _gpu_adjoint(probs, m, specialize=False):
     import torch
     from paper_2204_05586_amd import native
-    plan = native.AdjointPlan(probs, m)
+    plan = native.AdjointPlan(probs, m, specialize=specialize)
+    assert plan.specialized == specialize
     bufs = plan.allocate()
     print(f"[gpu] adjoint n={len(probs)} grads={plan.n_grad} ws={plan.ws_bytes}", flush=True)
     plan.run(bufs)
@@ -152,3 +153,29 @@ def test_autograd_descent_lowers_loss(torch_dev):
     print(f"descent losses {losses}", flush=True)
     assert all(b < a for a, b in zip(losses, losses[1:])), losses
     model.close()
+
+
+def test_compiled_forward_gives_the_same_gradients(torch_dev):
+    """The shared field program compiled into the forward pass: losses and
+    final states bit for bit those of the interpreted forward, gradients
+    equal up to the order of their FP64 atomic sums."""
+    probs = W.control_batch(seed=6, n_inst=16, n_samples=300, n_fine=40)
+    a = _gpu_adjoint(probs, 1)
+    b = _gpu_adjoint(probs, 1, specialize=True)
+    assert np.array_equal(a["loss"], b["loss"])
+    assert np.array_equal(a["psi_final"], b["psi_final"])
+    for ga, gb in zip(a["grad"], b["grad"]):
+        assert _rel(gb, ga) <= 1e-13
+
+
+def test_compiled_forward_needs_its_own_terms(torch_dev):
+    from paper_2204_05586_amd import native
+    probs = W.control_batch(seed=6, n_inst=2, n_samples=50, n_fine=10)
+    other = native.Sampler.for_terms(probs[0].terms[:1])
+    plan = native.AdjointPlan(probs, 1, specialize=False)
+    with pytest.raises(native.MssError, match="not generated from its terms"):
+        native.check(native.lib().mss_adjoint_plan_create_compiled(
+            2, plan._arr, plan.param_off.ctypes.data_as(native.C.POINTER(native.C.c_int64)), 1,
+            other._h, native.C.byref(native.C.c_void_p())))
+    plan.close()
+    other.close()

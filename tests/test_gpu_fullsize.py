@@ -118,12 +118,14 @@ def test_serving_stream_full(torch_dev, oracle):
 
 
 def test_control_gradients_full(torch_dev, oracle):
-    """All 1024 control instances (512 gradients each); three seeded
+    """All 1024 control instances (512 gradients each), the shared field
+    compiled into the forward pass as the bench runs them; three seeded
     instances against the oracle's adjoint."""
     import torch
     from paper_2204_05586_amd import native
     probs = W.control_batch(seed=4)
-    plan = native.AdjointPlan(probs, 1)
+    plan = native.AdjointPlan(probs, 1, specialize=True)
+    assert plan.specialized
     bufs = plan.allocate()
     print(f"[gpu] full control gradients n={len(probs)}", flush=True)
     plan.run(bufs)
