@@ -404,9 +404,15 @@ def bench_next_rows(reps: int = 20) -> dict:
 
     def timed(fn) -> float:
         # back-to-back launches between one pair of events: the per-launch
-        # time of short kernels without an event pair's own overhead
-        for _ in range(3):
+        # time of short kernels without an event pair's own overhead.  At
+        # least 0.2 s of warm-up first: a run-time compile just before leaves
+        # the GPU idle and its clock low.
+        t_warm, done = time.perf_counter(), 0
+        while done < 3 or time.perf_counter() - t_warm < 0.2:
             fn()
+            done += 1
+            if done % 16 == 0:
+                torch.cuda.synchronize()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -506,6 +512,11 @@ def accuracy_study(ref_fine: int = 500, reps: int = 3) -> dict:
         ref = torch.empty((K, N), dtype=torch.complex128, device="cuda")
         run(base.replace(n_fine=ref_fine), ref)
         psi = torch.empty_like(ref)
+        # 0.2 s of work first: the compile above left the GPU idle, its clock low
+        t_warm = time.perf_counter()
+        while time.perf_counter() - t_warm < 0.2:
+            run(base, psi)
+            torch.cuda.synchronize()
         series = {}
         for mname, method in (("cf4", W.CF4), ("midpoint", W.MIDPOINT), ("heun", W.HEUN)):
             for frame in (True, False):
