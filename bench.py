@@ -38,9 +38,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # sources are unchanged.
 MEASURED_TRAFFIC = {
     ("mss_user_work_integrate", "batched_sensing"): {
-        "src": "a400374b204b17d4",
-        "fetch_kib": 4502.25, "write_kib": 64034524.65625,
-        "bytes": int(round((4502.25 * 2.000 + 64034524.65625 * 1.000) * 1024)),
+        "src": "d894a1a6ee8ec244",
+        "fetch_kib": 4520.8125, "write_kib": 64034971.0,
+        "bytes": int(round((4520.8125 * 2.000 + 64034971.0 * 1.000) * 1024)),
     },
 }
 
