@@ -113,6 +113,25 @@ def test_errors_raise_as_python_kinds():
     assert isinstance(e.value, native.MssError)
 
 
+def test_compiled_adjoint_checks_its_sampler_before_any_allocation():
+    """mss_adjoint_plan_create_compiled refuses a NULL sampler and one not
+    generated from the problems' terms, before touching the device."""
+    probs = W.control_batch(seed=6, n_inst=2, n_samples=20, n_fine=4)
+    arr = (native.Problem * 2)()
+    packed = [native.PackedProblem(p) for p in probs]
+    for i, pk in enumerate(packed):
+        arr[i] = pk.c
+    offs = np.array([0, len(probs[0].params)], dtype=np.int64)
+    offp = offs.ctypes.data_as(C.POINTER(C.c_int64))
+    L = native.lib()
+    st = L.mss_adjoint_plan_create_compiled(2, arr, offp, 1, None, C.byref(C.c_void_p()))
+    assert st == native.MSS_E_INVALID and "NULL" in native.last_error()
+    other = native.Sampler.for_terms(probs[0].terms[:1])
+    st = L.mss_adjoint_plan_create_compiled(2, arr, offp, 1, other._h, C.byref(C.c_void_p()))
+    assert st == native.MSS_E_INVALID and "not generated from its terms" in native.last_error()
+    other.close()
+
+
 def test_propagate_spin_requires_output():
     L = native.lib()
     buf = (C.c_double * 64)()
