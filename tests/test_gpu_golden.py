@@ -1,0 +1,61 @@
+"""GPU: one CF4 fine step against exp(-i H2 dt) exp(-i H1 dt) built by
+scipy's expm from the sample times and weights the paper prints
+(tests/golden/), spin-1/2 and spin-1 with Q, lab frame and, for the frame,
+a whole interval of steps against the oracle-independent product of such
+steps (Sec. "Unitary time evolution and the Magnus expansion",
+eqs. cf4_sample_1/2, cf4_implementation)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2204_05586_amd import workloads as W
+from tests.test_oracle_golden import G, _random_terms, _spin_ops
+
+pytestmark = pytest.mark.gpu
+scipy_linalg = pytest.importorskip("scipy.linalg")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2204_05586_amd import native
+    native.lib()
+    return torch
+
+
+def _cf4_steps(field, ops, t0, dt, L):
+    """The printed CF4 step applied L times over [t0, t0 + L dt]."""
+    U = np.eye(ops[0].shape[0], dtype=complex)
+    for l in range(L):
+        t = t0 + l * dt
+
+        def H(s):
+            return 2 * math.pi * sum(f * A for f, A in zip(field(s), ops))
+        h1, h2 = H(t + G["c1"] * dt), H(t + G["c2"] * dt)
+        hb1 = G["w_plus"] * h1 + G["w_minus"] * h2
+        hb2 = G["w_minus"] * h1 + G["w_plus"] * h2
+        U = scipy_linalg.expm(-1j * hb2 * dt) @ scipy_linalg.expm(-1j * hb1 * dt) @ U
+    return U
+
+
+@pytest.mark.parametrize("spin_twice", [1, 2])
+def test_gpu_cf4_steps_from_printed_constants(dev, spin_twice):
+    torch = dev
+    from paper_2204_05586_amd import native
+    rng = np.random.default_rng(80 + spin_twice)
+    ops = _spin_ops(spin_twice)
+    N = spin_twice + 1
+    for trial in range(4):
+        terms, field = _random_terms(rng, spin_twice)
+        t0, Dt = rng.uniform(0, 1e-3), rng.uniform(2e-6, 2e-5)
+        L = (1, 3, 7, 16)[trial]
+        p = W.Problem(spin_twice, terms, t0, Dt, 1, L, 40, False)
+        U = torch.empty((1, N, N), dtype=torch.complex128, device="cuda")
+        print(f"[gpu] printed-constant CF4 spin_twice={spin_twice} L={L}", flush=True)
+        native.integrate(p, native.device_params(p), U)
+        torch.cuda.synchronize()
+        ref = _cf4_steps(field, ops, t0, Dt / L, L)
+        assert np.max(np.abs(U.cpu().numpy()[0] - ref)) < 1e-13, (spin_twice, L)
