@@ -91,3 +91,41 @@ def test_printed_constants_are_consistent():
     assert abs(G["c1"] + G["c2"] - 1.0) < 1e-15
     assert abs(G["q_diag_0"] + G["q_diag_1"] + G["q_diag_2"]) < 1e-15
     assert G["tau_default"] == 24
+
+
+def _frame_interval(field, ops, t0, Dt, L):
+    """exp(-i w_r Dt J_z) times L printed CF4 steps of the frame Hamiltonian
+    exp(i w_r s J_z) H exp(-i w_r s J_z) - w_r J_z, s measured from t0,
+    w_r = 2 pi f_z(t0 + Dt/2) (Sec. "Dynamically rotating frame")."""
+    jz = ops[2]
+    N = jz.shape[0]
+    wr = 2 * math.pi * field(t0 + Dt / 2)[2]
+    dt = Dt / L
+    Ur = np.eye(N, dtype=complex)
+    for l in range(L):
+        t = t0 + l * dt
+
+        def Hrot(s):
+            H = 2 * math.pi * sum(f * A for f, A in zip(field(s), ops))
+            R = scipy_linalg.expm(-1j * wr * (s - t0) * jz)
+            return R.conj().T @ H @ R - wr * jz
+        h1, h2 = Hrot(t + G["c1"] * dt), Hrot(t + G["c2"] * dt)
+        hb1 = G["w_plus"] * h1 + G["w_minus"] * h2
+        hb2 = G["w_minus"] * h1 + G["w_plus"] * h2
+        Ur = scipy_linalg.expm(-1j * hb2 * dt) @ scipy_linalg.expm(-1j * hb1 * dt) @ Ur
+    return scipy_linalg.expm(-1j * wr * Dt * jz) @ Ur
+
+
+@pytest.mark.parametrize("spin_twice", [1, 2])
+def test_rotating_frame_interval_from_printed_constants(oracle, spin_twice):
+    """The oracle's interval operator with the frame on equals the frame
+    built independently from its definition with scipy's expm (a wrong sign
+    of the frame phase, of w_r, or of the exit rotation fails this at O(1))."""
+    rng = np.random.default_rng(95 + spin_twice)
+    ops = _spin_ops(spin_twice)
+    for L in (1, 5, 12):
+        terms, field = _random_terms(rng, spin_twice)
+        t0, Dt = rng.uniform(0, 1e-3), rng.uniform(2e-6, 2e-5)
+        got = oracle.operators(W.Problem(spin_twice, terms, t0, Dt, 1, L, 40, True))[0]
+        ref = _frame_interval(field, ops, t0, Dt, L)
+        assert np.max(np.abs(got - ref)) < 5e-14, (spin_twice, L)
