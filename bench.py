@@ -62,6 +62,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# The paper's own speed figure, quoted as context (another GPU; not the
+# target): Sec. "Parallelization performance" runs its 100 ms spin-1 sensing
+# simulation at 100 ns steps (1e6 CF4 steps) almost twice as fast as real
+# time on an RTX 3080, about 50 ms, i.e. about 2e7 fine steps/s.
+PAPER_CONTEXT = {"workload": "one 100 ms spin-1 sensing simulation, 1e6 CF4 steps",
+                 "hardware": "GeForce RTX 3080", "ms": 50.0, "fine_steps_per_s": 2.0e7}
+
+
 def spin_one_flops_per_fine_step(tau: int) -> int:
     """Algorithmic FP64 flops of one spin-1 CF4 fine step as computed: two
     Lie-Trotter exponentials of tau residual squarings of a complex symmetric
@@ -696,6 +704,7 @@ def main():
         "next_rows": next_rows,
         "roofline": roofline,
         "cpu_baseline": base,
+        "paper_context": PAPER_CONTEXT,
         "kernel_src": src_hash,
     }
     print(json.dumps(out), flush=True)
