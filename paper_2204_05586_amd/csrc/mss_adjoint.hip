@@ -672,10 +672,16 @@ mss_status mss_adjoint_plan_create_compiled(int32_t n, const mss_problem* proble
   *out = nullptr;
   if (!forward) return api_fail(MSS_E_INVALID, "forward sampler is NULL");
   if (n < 1 || !problems) return api_fail(MSS_E_INVALID, "need at least one problem");
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
+    mss_status s = api_validate_problem(&problems[i]);
+    if (s != MSS_OK) {
+      std::string msg = api_last_error_copy();
+      return api_fail(s, "simulation %d: %s", i, msg.c_str());
+    }
     if (!api_sampler_is_for_terms(forward, problems[i].terms, problems[i].n_terms))
       return api_fail(MSS_E_INVALID,
                       "simulation %d: the forward sampler was not generated from its terms", i);
+  }
   mss_status s = mss_adjoint_plan_create(n, problems, param_off, level_m, out);
   if (s != MSS_OK) return s;
   (*out)->forward = forward;

@@ -130,6 +130,12 @@ def test_compiled_adjoint_checks_its_sampler_before_any_allocation():
     st = L.mss_adjoint_plan_create_compiled(2, arr, offp, 1, other._h, C.byref(C.c_void_p()))
     assert st == native.MSS_E_INVALID and "not generated from its terms" in native.last_error()
     other.close()
+    # a problem that claims terms but passes none is refused, not read
+    own = native.Sampler.for_terms(probs[0].terms)
+    arr[1].terms = None
+    st = L.mss_adjoint_plan_create_compiled(2, arr, offp, 1, own._h, C.byref(C.c_void_p()))
+    assert st == native.MSS_E_INVALID and "terms is NULL" in native.last_error()
+    own.close()
 
 
 def test_propagate_spin_requires_output():
