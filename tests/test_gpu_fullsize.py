@@ -82,6 +82,12 @@ def test_plain_sensing_full_compiled_field(torch_dev, oracle):
             np.max(np.abs(U.cpu().numpy() - ref["U"])))
     print(f"plain sensing, compiled field: max |d| = {d:.3e}", flush=True)
     assert d <= TOL
+    # every interval operator unitary: max |U^H U - I| over all 2e5 of them
+    uh = U.conj().transpose(-1, -2).contiguous()
+    eye = torch.eye(N, dtype=torch.complex128, device="cuda")
+    dev_u = float((torch.matmul(uh, U) - eye).abs().max())
+    print(f"plain sensing: max |U^H U - I| = {dev_u:.3e}", flush=True)
+    assert dev_u < 1e-12
     s.close()
 
 
