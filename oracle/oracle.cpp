@@ -219,13 +219,17 @@ template <class R> Dual<R> sqrt(const Dual<R>& a) {
   const R r = std::sqrt(a.v);
   return {r, a.dx / (R(2) * r), a.dy / (R(2) * r)};
 }
+// hypot and atan2 are not differentiable at x = y = 0; the spin-1 factor
+// that uses them is, and lie_trotter_residual takes that point apart.
 template <class R> Dual<R> hypot(const Dual<R>& x, const Dual<R>& y) {
   const R h = std::hypot(x.v, y.v);
-  return {h, (x.v * x.dx + y.v * y.dx) / h, (x.v * x.dy + y.v * y.dy) / h};
+  const R cx_ = x.v / h, sy = y.v / h;
+  return {h, cx_ * x.dx + sy * y.dx, cx_ * x.dy + sy * y.dy};
 }
 template <class R> Dual<R> atan2(const Dual<R>& y, const Dual<R>& x) {
-  const R r2 = x.v * x.v + y.v * y.v;
-  return {std::atan2(y.v, x.v), (x.v * y.dx - y.v * x.dx) / r2, (x.v * y.dy - y.v * x.dy) / r2};
+  const R h = std::hypot(x.v, y.v);
+  const R cx_ = x.v / h, sy = y.v / h;
+  return {std::atan2(y.v, x.v), (cx_ * y.dx - sy * x.dx) / h, (cx_ * y.dy - sy * x.dy) / h};
 }
 template <class R> Dual<R> ldexp(const Dual<R>& a, int e) {
   return {std::ldexp(a.v, e), std::ldexp(a.dx, e), std::ldexp(a.dy, e)};
@@ -257,12 +261,19 @@ Mat<R, N> matmul(const Mat<R, N>& A, const Mat<R, N>& B) {
 
 // ---- exponentiators ---------------------------------------------------------
 // Spin-1/2: exp(-i (theta_x J_x + theta_y J_y + theta_z J_z)), J = sigma / 2.
+// At theta = 0 the formula is taken at its limit, cos -> 1 and
+// sin(|theta|/2)/|theta| -> 1/2: E = I, and with dual numbers the tangent
+// -i sigma_a / 2 along theta_a (the map is analytic there; the square root
+// of |theta|^2 is not).
 template <class R>
 Mat<R, 2> exp_half(const R th[3]) {
-  R big = sqrt(th[0] * th[0] + th[1] * th[1] + th[2] * th[2]);
-  if (big == R(0)) return Mat<R, 2>::identity();
-  R c = cos(big / R(2));
-  R s = sin(big / R(2)) / big;
+  const R big2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+  R c = R(1), s = R(1) / R(2);
+  if (big2 != R(0)) {
+    const R big = sqrt(big2);
+    c = cos(big / R(2));
+    s = sin(big / R(2)) / big;
+  }
   Mat<R, 2> e;
   e.m[0][0] = cx<R>(c, -s * th[2]);
   e.m[0][1] = cx<R>(-s * th[1], -s * th[0]);
@@ -278,15 +289,11 @@ cx<R> expim1(R beta) {
   return cx<R>(R(-2) * h * h, sin(beta));
 }
 
-// Residual a = T - I of the symmetric Lie-Trotter factor for the step angles
-// theta = (theta_x, theta_y, theta_z, theta_q) and n = 2^tau.
+// Residual a = T - I of the symmetric Lie-Trotter factor (eq. lie_trotter_4,
+// corrected) from z = theta_z / n, q = theta_q / n, Phi and e^{i phi}.
 template <class R>
-Mat<R, 3> lie_trotter_residual(const R th[4], int tau) {
-  const R n = ldexp(R(1), tau);
-  const R z = th[2] / n;
-  const R q = th[3] / n;
-  const R Phi = hypot(th[0], th[1]) / n;
-  const R phi = atan2(th[1], th[0]);
+Mat<R, 3> lie_trotter_residual_polar(R z, R q, R Phi, cx<R> eiphi) {
+  const cx<R> emphi = std::conj(eiphi);  // e^{-i phi}
   const R C = cos(Phi / R(2));
   const R S = sin(Phi / R(2));
   const R sPhi = sin(Phi);
@@ -296,14 +303,14 @@ Mat<R, 3> lie_trotter_residual(const R th[4], int tau) {
   const cx<R> off = mi * cx<R>(r * sPhi, R(0));  // (-i / sqrt 2) sin(Phi)
   Mat<R, 3> a;
   // off-diagonal entries of T (eq. lie_trotter_4, corrected)
-  a.m[0][1] = off * expi(q / R(6)) * expi(-z / R(2)) * expi(-phi);
-  a.m[1][0] = off * expi(q / R(6)) * expi(-z / R(2)) * expi(phi);
-  a.m[1][2] = off * expi(q / R(6)) * expi(z / R(2)) * expi(-phi);
-  a.m[2][1] = off * expi(q / R(6)) * expi(z / R(2)) * expi(phi);
+  a.m[0][1] = off * expi(q / R(6)) * expi(-z / R(2)) * emphi;
+  a.m[1][0] = off * expi(q / R(6)) * expi(-z / R(2)) * eiphi;
+  a.m[1][2] = off * expi(q / R(6)) * expi(z / R(2)) * emphi;
+  a.m[2][1] = off * expi(q / R(6)) * expi(z / R(2)) * eiphi;
   {
-    cx<R> w = cx<R>(S, R(0)) * expi(-q / R(6)) * expi(-phi);
+    cx<R> w = cx<R>(S, R(0)) * expi(-q / R(6)) * emphi;
     a.m[0][2] = -(w * w);
-    cx<R> v = cx<R>(S, R(0)) * expi(-q / R(6)) * expi(phi);
+    cx<R> v = cx<R>(S, R(0)) * expi(-q / R(6)) * eiphi;
     a.m[2][0] = -(v * v);
   }
   // diagonal entries of T - I: T_11 = C^2 e^{i b1}, T_22 = cos(Phi) e^{i b2},
@@ -315,6 +322,47 @@ Mat<R, 3> lie_trotter_residual(const R th[4], int tau) {
   a.m[0][0] = expim1(b1) - cx<R>(S2, R(0)) * expi(b1);
   a.m[1][1] = expim1(b2) - cx<R>(R(2) * S2, R(0)) * expi(b2);
   a.m[2][2] = expim1(b3) - cx<R>(S2, R(0)) * expi(b3);
+  return a;
+}
+
+// The same for the step angles theta = (theta_x, theta_y, theta_z, theta_q)
+// and n = 2^tau: Phi = rho / n with rho = |theta_x + i theta_y| and
+// phi = atan2(theta_y, theta_x) (Sec. "Lie-Trotter based exponentiator";
+// phi = atan2(0, 0) = 0 at rho = 0).
+template <class R>
+Mat<R, 3> lie_trotter_residual(const R th[4], int tau) {
+  const R n = ldexp(R(1), tau);
+  const R phi = atan2(th[1], th[0]);
+  return lie_trotter_residual_polar(th[2] / n, th[3] / n, hypot(th[0], th[1]) / n, expi(phi));
+}
+
+// Dual numbers at rho = 0, where Phi and phi have no derivative but T has:
+// on the line theta_y = 0 the form at phi = 0 with the signed Phi = theta_x / n
+// is T itself (a negative Phi at phi = 0 gives the entries of |Phi| at
+// phi = pi), so its tangent is the theta_x part of dT; on theta_x = 0 the
+// form at phi = pi/2 (e^{i phi} = i) with Phi = theta_y / n gives the theta_y
+// part.  Both evaluate T at Phi = 0, where it does not depend on phi, and the
+// chain rule adds the two tangents.
+template <class R>
+Mat<Dual<R>, 3> lie_trotter_residual(const Dual<R> th[4], int tau) {
+  if (std::hypot(th[0].v, th[1].v) != R(0)) {
+    const Dual<R> n = ldexp(Dual<R>(R(1)), tau);
+    const Dual<R> phi = atan2(th[1], th[0]);
+    return lie_trotter_residual_polar(th[2] / n, th[3] / n, hypot(th[0], th[1]) / n, expi(phi));
+  }
+  using D = Dual<R>;
+  const R n = std::ldexp(R(1), tau);
+  const cx<D> one(D(R(1)), D(R(0))), i_(D(R(0)), D(R(1)));
+  const Mat<D, 3> ax = lie_trotter_residual_polar(th[2] / D(n), th[3] / D(n), th[0] / D(n), one);
+  const Mat<D, 3> ay = lie_trotter_residual_polar(D(th[2].v / n), D(th[3].v / n), th[1] / D(n), i_);
+  Mat<D, 3> a;
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) {
+      const cx<D>& x = ax.m[j][k];
+      const cx<D>& y = ay.m[j][k];
+      a.m[j][k] = cx<D>(D(x.real().v, x.real().dx + y.real().dx, x.real().dy + y.real().dy),
+                        D(x.imag().v, x.imag().dx + y.imag().dx, x.imag().dy + y.imag().dy));
+    }
   return a;
 }
 
