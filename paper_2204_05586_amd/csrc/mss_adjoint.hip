@@ -38,7 +38,10 @@ namespace mss {
 // closed form, dE_jk/d phi = -i (m_j - m_k) E_jk, and
 //   dE/dtheta_x = cos(phi) dE/drho - (sin(phi) / rho) dE/dphi,
 //   dE/dtheta_y = sin(phi) dE/drho + (cos(phi) / rho) dE/dphi.
-// Both derivatives are taken as 0 at rho = 0.
+// At rho = 0 phi has no derivative, but E is analytic in theta_x, theta_y:
+// along +theta_x (phi = 0) dE/dtheta_x = dE/drho = G, and along +theta_y
+// dE/dtheta_y = P(pi/2) G P(pi/2)^H, whose entries are -i (m_j - m_k) G_jk
+// (the limit of (1 / rho) dE/dphi; G has a zero diagonal and G_13 = 0 there).
 // ---------------------------------------------------------------------------
 
 // d a' / d rho of the residual of lie_trotter_residual, term by term from
@@ -126,8 +129,9 @@ __device__ __forceinline__ void tangent_square(const Sym3& a, const Sym3& d, Sym
 // E = exp of the step angles (Lie-Trotter, tau residual squarings) with
 // G = dE/drho, the derivative of exactly the computed E, and the chain
 // coefficients c = (d rho / d theta_x, d rho / d theta_y, d phi / d theta_x,
-// d phi / d theta_y), all 0 at rho = 0.
-__device__ __forceinline__ void exp_one_tangent(const double th[4], int tau, Mat<3>& E, Mat<3>& G,
+// d phi / d theta_y).  Returns false at rho = 0, where c is not defined and
+// the angle derivatives come from G alone.
+__device__ __forceinline__ bool exp_one_tangent(const double th[4], int tau, Mat<3>& E, Mat<3>& G,
                                                 double c[4]) {
   // Three register sets rotate: a step reads (a, d) and writes the new
   // tangent over the free set, then the new residual over d, which the
@@ -164,13 +168,13 @@ __device__ __forceinline__ void exp_one_tangent(const double th[4], int tau, Mat
   }
   const double rho = sqrt(fma(th[0], th[0], th[1] * th[1]));
   c[0] = c[1] = c[2] = c[3] = 0.0;
-  if (rho > 0.0) {
-    const double inv = 1.0 / rho;
-    c[0] = epr;
-    c[1] = epi;
-    c[2] = -epi * inv;
-    c[3] = epr * inv;
-  }
+  if (!(rho > 0.0)) return false;
+  const double inv = 1.0 / rho;
+  c[0] = epr;
+  c[1] = epi;
+  c[2] = -epi * inv;
+  c[3] = epr * inv;
+  return true;
 }
 
 // Spin-1/2: E = cos(|theta|/2) I - i (sin(|theta|/2)/|theta|) theta.sigma and
@@ -297,12 +301,17 @@ template <> struct TangentStep<3> {
                                                double* nlr, double* nli, double* gx, double* gy) {
     Mat<3> E, G;
     double c[4];
-    exp_one_tangent(th, tau, E, G, c);
+    const bool polar = exp_one_tangent(th, tau, E, G, c);
     mat_h_vec<3>(E, pr, pi, br, bi);
     const double grho = bilinear<3>(lr, li, G, br, bi);
-    const double gphi = bilinear_phi(lr, li, E, br, bi);
-    *gx = fma(c[0], grho, c[2] * gphi);
-    *gy = fma(c[1], grho, c[3] * gphi);
+    if (polar) {
+      const double gphi = bilinear_phi(lr, li, E, br, bi);
+      *gx = fma(c[0], grho, c[2] * gphi);
+      *gy = fma(c[1], grho, c[3] * gphi);
+    } else {  // rho = 0: dE/dtheta_x = G, dE/dtheta_y = -i (m_j - m_k) G_jk
+      *gx = grho;
+      *gy = bilinear_phi(lr, li, G, br, bi);
+    }
     mat_h_vec<3>(E, lr, li, nlr, nli);
   }
 };

@@ -4,7 +4,8 @@ import numpy as np
 import pytest
 
 from paper_2204_05586_amd import workloads as W
-from tests.test_oracle_adjoint import _control_problem
+from tests.test_oracle_adjoint import (_central_differences, _control_problem,
+                                       _zero_field_problem, per_component_ok)
 
 pytestmark = pytest.mark.gpu
 
@@ -53,6 +54,29 @@ def test_adjoint_matches_oracle_small(torch_dev, oracle):
         r = _rel(g["grad"][i], grad)
         print(f"adjoint {i}: loss {loss:.6f} rel grad err {r:.2e}", flush=True)
         assert r <= 1e-9, (i, r)
+
+
+def test_adjoint_at_zero_transverse_field(torch_dev, oracle):
+    """Segments with no transverse field (rho = 0) and no field at all
+    (theta = 0), both spins, frame on and off, random psi0, in one adjoint
+    plan: the GPU gradients against the oracle adjoint (rel 1e-9 of the
+    largest entry) and, per component, against extended-precision central
+    differences (rel 1e-6)."""
+    cases = [(2, True), (2, False), (1, True), (1, False)]
+    probs = [_zero_field_problem(s, f, seed=3 * s + f) for s, f in cases]
+    for m in (1, 0):
+        g = _gpu_adjoint(probs, m)
+        for i, p in enumerate(probs):
+            assert np.all(np.isfinite(g["grad"][i]))
+            loss, grad = oracle.adjoint_population(p, m)
+            assert abs(g["loss"][i] - loss) < 1e-12
+            r = _rel(g["grad"][i], grad)
+            fd = _central_differences(oracle, p, m)
+            ok, worst = per_component_ok(g["grad"][i], fd)
+            print(f"zero field {cases[i]} m={m}: rel vs oracle {r:.2e}, "
+                  f"worst/bound vs differences {worst:.2e}", flush=True)
+            assert r <= 1e-9, (cases[i], m, r)
+            assert ok, (cases[i], m, g["grad"][i], fd)
 
 
 def test_adjoint_control_workload_subset(torch_dev, oracle):
