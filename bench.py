@@ -3,17 +3,22 @@
 
 Default workload: 4096 spin-1 sensing simulations of uneven length (10-100
 ms at 5e-7 s output steps, 10 CF4 steps per interval, tau = 28, rotating
-frame) run as one batch: the persistent integrator (interval operators from
-CF4 fine steps) followed by the segmented scan (states psi_k), both through
-the C ABI.  The simulations share one field program (their parameters
-differ), which the plan compiles into the integrator at creation
-(mss_sampler_create_for_terms; the interpreter's time is reported beside it).
-One step = one pass over the whole batch.  Inputs and outputs stay resident
-in HBM; the timed region starts after they are allocated.
+frame) run as one batch: one captured HIP graph of the chained persistent
+integrator, which builds every interval operator from its CF4 fine steps
+and forms the states psi_k in the same launch (work items pass their
+leaving state on to the next item of their simulation), through the C ABI.
+The simulations share one field program (their parameters differ), which
+the plan compiles into the integrator at creation
+(mss_sampler_create_for_terms; the interpreter's time is reported beside
+it).  One step = one replay of the graph over the whole batch.  Inputs and
+outputs stay resident in HBM; the timed region starts after they are
+allocated.
 
-Also measured in the same run: the plain path (one simulation per launch
-sequence) on the single spin-1 sensing simulation, and the batch replayed as
-one captured HIP graph.
+Also measured in the same run: the separate-scan form of the batch
+(operators kept in HBM, then the segmented scan), the plain path (one
+simulation per launch sequence) on the single spin-1 sensing simulation and
+the spin-1/2 Rabi simulation, the rows beyond the hot path, the adjoint and
+the serving sweep.
 
 Prints one JSON line: CF4 fine steps/s, the integrator's roofline figures
 (algorithmic FP64 flops / measured kernel time vs the 78.6 TFLOP/s FP64
@@ -78,6 +83,11 @@ def spin_one_flops_per_fine_step(tau: int) -> int:
     (27 complex multiply-adds = 216 flops each).  Angle set-up and the
     phases put back once per exponential are not counted."""
     return 2 * tau * 96 + 2 * 216
+
+
+# Algorithmic FP64 flops of one state update psi_{k+1} = U_k psi_k (spin-1:
+# 9 complex multiply-adds of 8 flops each).
+STATE_UPDATE_FLOPS = 72
 
 
 def cpu_baseline(problems, seconds: float) -> dict:
@@ -195,82 +205,96 @@ def bench_plain(prob, steps: int, warmup: int, specialise: bool = True) -> dict:
             "launch": {"slices": launch[0], "block": launch[1]}, "tau": prob.n_squares}
 
 
-def bench_batched(problems, steps: int, warmup: int, graph_reps: int, tune: bool,
-                  specialise: bool = True) -> dict:
-    """The batch plan (the shared field program compiled into the persistent
-    integrator, unless specialise is off); the interpreter's integrator is
-    timed on the same buffers too."""
+def bench_batched(problems, steps: int, warmup: int, tune: bool, specialise: bool = True,
+                  separate_reps: int = 3) -> dict:
+    """The batch as one captured HIP graph of a chained plan (the shared
+    field program compiled into the persistent integrator, which also forms
+    the states; no operator buffer), replayed `steps` times after at least
+    3 warm-up replays, each replay between HIP events on the stream it runs
+    on.  Then the separate-scan plan (operators kept in the workspace, then
+    the segmented scan) eagerly, integrator and scan timed apart, and the
+    interpreter's integrator on its buffers."""
     import torch
     from paper_2204_05586_amd import autotune, native
     t0 = time.perf_counter()
     opts = autotune.tune(problems, cache_path=None, specialize=specialise) if tune else {}
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plan = native.BatchPlan(problems, specialize=specialise, **opts)
+    plan = native.BatchPlan(problems, specialize=specialise, chained=True, use_graph=True, **opts)
     compile_s = time.perf_counter() - t0
     bufs = plan.allocate(store_u=False)
     stream = torch.cuda.current_stream()
     fine = sum(p.fine_steps for p in problems)
-
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        plan.integrate(bufs, stream=stream)
-        if ev:
-            ev[1].record(stream)
-        plan.propagate(bufs, stream=stream)
-        if ev:
-            ev[2].record(stream)
-
-    for _ in range(warmup):
-        step()
+    for _ in range(max(warmup, 3)):  # the first run captures the graph
+        plan.run(bufs, stream=stream)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
     t0 = time.perf_counter()
-    for e in evs:
-        step(e)
+    for a, b in evs:
+        a.record(stream)
+        plan.run(bufs, stream=stream)
+        b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    integ = [e[0].elapsed_time(e[1]) for e in evs]
-    prop = [e[1].elapsed_time(e[2]) for e in evs]
+    replay = [a.elapsed_time(b) for a, b in evs]
     info = plan.info()
     specialized = plan.specialized
+    ws_bytes = int(bufs["ws"].numel())
+    psi_chained = bufs["psi"]
     plan.close()
+    del bufs["ws"]
+    # the separate-scan plan: integrator then scan, eager
+    sep = native.BatchPlan(problems, specialize=specialise, **opts)
+    sbufs = sep.allocate(store_u=False)
+    integ, prop = [], []
+    for rep in range(separate_reps + 1):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        sep.integrate(sbufs, stream=stream)
+        e[1].record(stream)
+        sep.propagate(sbufs, stream=stream)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        if rep:  # the first is a warm-up
+            integ.append(e[0].elapsed_time(e[1]))
+            prop.append(e[1].elapsed_time(e[2]))
+    d_sep = float((sbufs["psi"] - psi_chained).abs().max())
+    sep_ws = int(sbufs["ws"].numel())
+    sep.close()
     iplan = native.BatchPlan(problems, **opts)
     interp = []
     for _ in range(2):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        iplan.integrate(bufs, stream=stream)
+        iplan.integrate(sbufs, stream=stream)
         e1.record(stream)
         interp.append((e0, e1))
     torch.cuda.synchronize()
     iplan.close()
-    out = {"value": fine * steps / wall, "ms_per_step": wall / steps * 1e3,
-           "integrate_ms": statistics.mean(integ), "propagate_ms": statistics.mean(prop),
-           "integrate_ms_interpreter": statistics.mean(a.elapsed_time(b) for a, b in interp),
-           "specialized": specialized, "compile_s": compile_s,
-           "fine_steps": fine, "info": info, "options": opts, "tune_s": tune_s}
-    if graph_reps > 0:
-        gplan = native.BatchPlan(problems, use_graph=True, specialize=specialise, **opts)
-        gplan.run(bufs, stream=stream)  # capture + first replay
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(graph_reps):
-            gplan.run(bufs, stream=stream)
-        torch.cuda.synchronize()
-        out["graph_ms_per_step"] = (time.perf_counter() - t0) / graph_reps * 1e3
-        gplan.close()
-    del bufs
+    del sbufs, psi_chained
     torch.cuda.empty_cache()
-    return out
+    return {"value": fine * steps / wall, "ms_per_step": wall / steps * 1e3,
+            "replay_ms_mean": statistics.mean(replay),
+            "replay_ms_median": statistics.median(replay),
+            "replay_ms_min": min(replay), "replay_ms_max": max(replay),
+            "workspace_bytes": ws_bytes,
+            "separate_scan": {"integrate_ms": statistics.mean(integ),
+                              "propagate_ms": statistics.mean(prop),
+                              "ms_per_step": statistics.mean(integ) + statistics.mean(prop),
+                              "workspace_bytes": sep_ws,
+                              "max_abs_diff_vs_chained": d_sep},
+            "integrate_ms_interpreter": statistics.mean(a.elapsed_time(b) for a, b in interp),
+            "specialized": specialized, "compile_s": compile_s,
+            "fine_steps": fine, "info": info, "options": opts, "tune_s": tune_s}
 
 
 def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib: float,
-                  burst: int = 0) -> dict:
+                  burst: int = 0, min_requests: int = 600) -> dict:
     """Poisson request streams (70 % spin-1, 30 % spin-1/2, K log-uniform in
     [1e3, 1e6], 10 CF4 steps per interval) submitted at their arrival times
-    to one server; latency = completion - scheduled arrival.  With burst > 0,
+    to one server; latency = completion - scheduled arrival.  Each rate gets
+    rate x seconds_per_rate requests, at least min_requests (so that p99 rests
+    on several samples) and at most max_requests.  With burst > 0,
     also `burst` requests of the same mix submitted at once: the server's
     capacity (fine steps/s from the first submission to the last
     completion), with latency = completion - submission."""
@@ -282,7 +306,7 @@ def bench_serving(rates, seconds_per_rate: float, max_requests: int, budget_gib:
     srv = native.Server(hbm_budget=int(budget_gib * (1 << 30)))
     out = {}
     for rate in rates:
-        n = int(min(max_requests, max(50, rate * seconds_per_rate)))
+        n = int(min(max_requests, max(min_requests, rate * seconds_per_rate)))
         idx = all_rates.index(rate) if rate in all_rates else len(all_rates)
         stream = W.serving_stream(rate, n_requests=n, rate_index=idx)
         q, records = queue.Queue(), []
@@ -560,18 +584,18 @@ def main():
                     choices=["batched_sensing", "spin_one_sensing", "spin_half_rabi"])
     ap.add_argument("--n-sims", type=int, default=4096, help="batch size of batched_sensing")
     ap.add_argument("--plain-steps", type=int, default=20)
-    ap.add_argument("--graph-reps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="planner defaults, no autotuning")
     ap.add_argument("--interpret", action="store_true",
                     help="interpret the field program instead of compiling it into the integrator")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
                     help="target CPU seconds of the oracle sample (0: skip)")
-    ap.add_argument("--serve-rates", default="10,100,1000",
+    ap.add_argument("--serve-rates", default="10,30,100,300,1000",
                     help="request rates (req/s) of the serving sweep, '' to skip")
     ap.add_argument("--serve-burst", type=int, default=300,
                     help="requests submitted at once to measure the server's capacity (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
-                    help="target stream length per rate (requests = rate x seconds, <= 2000)")
+                    help="target stream length per rate (requests = rate x seconds, "
+                         "600 <= requests <= 2000)")
     ap.add_argument("--adjoint-instances", type=int, default=1024,
                     help="instances of the control-gradient workload (0: skip)")
     ap.add_argument("--no-next-rows", action="store_true",
@@ -594,31 +618,36 @@ def main():
     if args.workload == "batched_sensing":
         problems = W.batched_sensing(seed=2, n_sims=args.n_sims)
         tau = problems[0].n_squares
-        res = bench_batched(problems, args.steps, args.warmup, args.graph_reps, not args.no_tune,
+        res = bench_batched(problems, args.steps, args.warmup, not args.no_tune,
                             not args.interpret)
-        kernel = "mss_user_work_integrate" if res["specialized"] else "work_integrate_kernel"
+        kernel = "mss_user_work_chained" if res["specialized"] else "work_chained_kernel"
         plain = (bench_plain(W.spin_one_sensing(), args.plain_steps, 3, not args.interpret)
                  if args.plain_steps > 0 else None)
         # the spin-1/2 Rabi simulation (1e4 samples x 100 fine steps) the same way
         plain_half = (bench_plain(W.spin_half_rabi(), args.plain_steps, 3, not args.interpret)
                       if args.plain_steps > 0 else None)
-        value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["integrate_ms"], \
+        value, ms, integ_ms, fine = res["value"], res["ms_per_step"], res["replay_ms_mean"], \
             res["fine_steps"]
+        intervals = res["info"]["total_samples"]
+        sep = res["separate_scan"]
         config = {"workload": f"batched_sensing: {len(problems)} spin-1 simulations, seed 2, "
                               f"durations U(10,100) ms, dt_out 5e-7 s",
-                  "mode": ("batched (field program compiled into the persistent integrator"
-                           if res["specialized"] else "batched (field program interpreted by the "
-                           "persistent integrator") + " + segmented scan, eager launches)",
+                  "mode": ("one captured HIP graph of the chained persistent integrator (field "
+                           "program " + ("compiled in" if res["specialized"] else "interpreted")
+                           + "), states formed in the same launch; replays timed"),
                   "compile_s": round(res["compile_s"], 2),
-                  "n_sims": len(problems), "total_intervals": res["info"]["total_samples"],
+                  "n_sims": len(problems), "total_intervals": intervals,
                   "n_fine": 10, "fine_steps": fine, "n_squares": tau, "rotating_frame": True,
                   "work_items": res["info"]["n_items"], "grid_blocks": res["info"]["grid_blocks"],
-                  "scan_levels": res["info"]["scan_levels"], "autotuned": res["options"],
-                  "autotune_s": round(res["tune_s"], 2)}
-        extra = {"integrate_ms_mean": round(integ_ms, 3),
+                  "autotuned": res["options"], "autotune_s": round(res["tune_s"], 2),
+                  "workspace_bytes": res["workspace_bytes"]}
+        extra = {"replay_ms_mean": round(res["replay_ms_mean"], 3),
+                 "replay_ms_median": round(res["replay_ms_median"], 3),
+                 "replay_ms_min": round(res["replay_ms_min"], 3),
+                 "replay_ms_max": round(res["replay_ms_max"], 3),
+                 "separate_scan": {k: (round(v, 3) if isinstance(v, float) and k.endswith("ms")
+                                       else v) for k, v in sep.items()},
                  "integrate_ms_interpreter": round(res["integrate_ms_interpreter"], 3),
-                 "propagate_ms_mean": round(res["propagate_ms"], 3),
-                 "graph_ms_per_step": round(res.get("graph_ms_per_step", 0.0), 3) or None,
                  "plain": ({k: (round(v, 4) if isinstance(v, float) else v)
                             for k, v in plain.items()} if plain else None),
                  "batched_over_plain": round(value / plain["value"], 3) if plain else None,
@@ -648,6 +677,8 @@ def main():
     roofline = None
     if args.workload != "spin_half_rabi":
         flops = spin_one_flops_per_fine_step(tau) * fine
+        if args.workload == "batched_sensing":
+            flops += STATE_UPDATE_FLOPS * intervals  # the states, formed in the same launch
         achieved = flops / (integ_ms * 1e-3) / 1e12
         traffic = MEASURED_TRAFFIC.get((kernel, args.workload))
         roofline = {"bound": "alu", "achieved": round(achieved, 3),

@@ -312,6 +312,14 @@ typedef struct mss_batch_options {
   int32_t use_graph;        /* 1: capture the batch as one HIP graph, replayed while the
                                buffer pointers stay the same */
   int32_t scan_per_lane;    /* operators per lane in the scan tiles: 2, 4 or 8 (0: 4) */
+  int32_t chained;          /* 1: mss_batch_run forms the states inside the integrator's
+                               launch: each work item multiplies its operators together in
+                               registers and passes its leaving state to the next item of its
+                               simulation, items being taken round by round across the
+                               simulations; no operator buffer and no scan (U, when given, is
+                               still written).  The workspace is then a 256-byte head plus 64
+                               bytes per simulation, mss_batch_propagate is not available and
+                               mss_batch_integrate needs U.  0: separate scan. */
 } mss_batch_options;
 
 typedef struct mss_batch_info_t {

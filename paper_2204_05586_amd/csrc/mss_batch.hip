@@ -28,6 +28,7 @@ struct mss_batch_plan {
   void* desc = nullptr;
   size_t o_sims = 0, o_terms = 0;
   std::vector<size_t> o_reduce, o_apply;
+  size_t o_chain = 0;
   std::vector<char> image;
   DevWork dev;
   const void* uploaded[6] = {};
@@ -54,13 +55,18 @@ void release(mss_batch_plan* p) {
 }
 
 // Workspace: counter (256 B) | operators, when the caller keeps no U |
-// per-simulation scan scratch.
+// per-simulation scan scratch.  Chained plans: the chain head and slots.
 size_t scan_base(const mss_batch_plan* P, bool store_u) {
   return 256 + (store_u ? 0 : a256((size_t)P->op_total * 16));
 }
 
+size_t ws_need(const mss_batch_plan* P, bool store_u) {
+  if (P->work.chained) return chain_workspace_bytes(P->n);
+  return scan_base(P, store_u) + P->scan_bytes;
+}
+
 mss_status check_ws(const mss_batch_plan* P, bool store_u, const void* ws, size_t ws_bytes) {
-  const size_t need = scan_base(P, store_u) + P->scan_bytes;
+  const size_t need = ws_need(P, store_u);
   if (!ws || ws_bytes < need)
     return api_fail(MSS_E_NOMEM, "workspace too small: need %zu bytes, got %zu", need,
                     ws ? ws_bytes : (size_t)0);
@@ -78,7 +84,8 @@ T* shift(T* base, int64_t off) {
 mss_status bind(mss_batch_plan* P, const double* params, const double* psi0, double* psi,
                 double* psi_final, double* U, void* ws) {
   char* base = (char*)ws;
-  double* ops = U ? U : (double*)(base + 256);
+  const bool chained = P->work.chained;
+  double* ops = (U || chained) ? U : (double*)(base + 256);
   const void* key[6] = {params, psi0, psi, psi_final, ops, ws};
   bool same = P->have_upload;
   for (int i = 0; i < 6 && same; ++i) same = P->uploaded[i] == key[i];
@@ -94,10 +101,10 @@ mss_status bind(mss_batch_plan* P, const double* params, const double* psi0, dou
     d.psi0 = shift(psi0, 2 * P->psi0_off[i]);
     d.psi = shift(psi, 2 * P->state_off[i]);
     d.psi_final = shift(psi_final, 2 * P->psi0_off[i]);
-    d.U = ops + 2 * P->op_off[i];
-    d.scan_ws = (double*)(base + sb + P->scan_off[i]);
+    d.U = shift(ops, 2 * P->op_off[i]);
+    d.scan_ws = chained ? nullptr : (double*)(base + sb + P->scan_off[i]);
   }
-  P->work.pack(P->image.data(), &P->o_sims, &P->o_terms, &P->o_reduce, &P->o_apply);
+  P->work.pack(P->image.data(), &P->o_sims, &P->o_terms, &P->o_reduce, &P->o_apply, &P->o_chain);
   hipError_t e = hipMemcpy(P->desc, P->image.data(), P->image.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return api_hip_fail(e, "descriptor upload");
   for (int i = 0; i < 6; ++i) P->uploaded[i] = key[i];
@@ -106,20 +113,30 @@ mss_status bind(mss_batch_plan* P, const double* params, const double* psi0, dou
 }
 
 // The sampler's work integrator on the current device (null without one).
-mss_status user_function(mss_batch_plan* P, hipFunction_t* fn) {
+mss_status user_function(mss_batch_plan* P, hipFunction_t* fn, bool chained = false) {
   *fn = nullptr;
-  return P->sampler ? api_sampler_work_function(P->sampler, fn) : MSS_OK;
+  return P->sampler ? api_sampler_work_function(P->sampler, fn, chained) : MSS_OK;
+}
+
+// The whole batch (integrate and scan, or one chained launch) or one half.
+hipError_t launch_batch(mss_batch_plan* P, bool integrate, bool scan, void* ws, hipFunction_t fn,
+                        hipStream_t st) {
+  if (P->work.chained && integrate && scan)
+    return launch_work_chained(P->dev, ws, P->grid_blocks, st, fn);
+  hipError_t e = hipSuccess;
+  if (integrate) e = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks, st, fn);
+  if (e == hipSuccess && scan) e = launch_work_scan(P->dev, st);
+  return e;
 }
 
 mss_status enqueue(mss_batch_plan* P, bool integrate, bool scan, void* ws, hipStream_t st) {
   hipError_t e = hipSuccess;
   hipFunction_t fn = nullptr;
   if (integrate) {
-    mss_status s = user_function(P, &fn);
+    mss_status s = user_function(P, &fn, P->work.chained && scan);
     if (s != MSS_OK) return s;
-    e = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks, st, fn);
   }
-  if (e == hipSuccess && scan) e = launch_work_scan(P->dev, st);
+  e = launch_batch(P, integrate, scan, ws, fn, st);
   if (e == hipSuccess) e = hipEventRecord(P->last_run, st);
   if (e != hipSuccess) return api_hip_fail(e, "batch launch");
   return MSS_OK;
@@ -142,6 +159,8 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
   if (opt.scan_per_lane != 0 && opt.scan_per_lane != 2 && opt.scan_per_lane != 4 &&
       opt.scan_per_lane != 8)
     return api_fail(MSS_E_INVALID, "scan_per_lane must be 0, 2, 4 or 8");
+  if (opt.chained != 0 && opt.chained != 1)
+    return api_fail(MSS_E_INVALID, "chained must be 0 or 1");
   const int scan_e = opt.scan_per_lane ? opt.scan_per_lane : kScanPerLane;
   for (int i = 0; i < n; ++i) {
     mss_status s = api_validate_problem(&problems[i]);
@@ -173,6 +192,7 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
   P->opt = opt;
   P->sampler = sampler;
   P->work.scan_e = scan_e;
+  P->work.chained = opt.chained != 0;
   P->psi0_off.assign(n + 1, 0);
   P->state_off.assign(n + 1, 0);
   P->op_off.assign(n + 1, 0);
@@ -187,16 +207,16 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
     P->op_off[i + 1] = P->op_off[i] + q.n_samples * N * N;
     P->param_off[i] = q.n_params > 0 ? param_off[i] : 0;
     P->scan_off[i] = scan;
-    scan += scan_scratch_bytes(N, q.n_samples, 64 * scan_e);
+    if (!P->work.chained) scan += scan_scratch_bytes(N, q.n_samples, 64 * scan_e);
     int S = S_class[q.spin_twice - 1];
     while (S > q.n_fine) S >>= 1;
-    P->work.add(q, api_ilog2(S), 0, q.n_samples, true);
+    P->work.add(q, api_ilog2(S), 0, q.n_samples, !P->work.chained);
   }
   P->work.finalize();
   P->scan_bytes = scan;
   P->op_total = P->op_off[n];
   P->image.resize(P->work.packed_bytes());
-  P->work.pack(P->image.data(), &P->o_sims, &P->o_terms, &P->o_reduce, &P->o_apply);
+  P->work.pack(P->image.data(), &P->o_sims, &P->o_terms, &P->o_reduce, &P->o_apply, &P->o_chain);
   hipError_t e = hipMalloc(&P->desc, P->image.size());
   if (e == hipSuccess) e = hipEventCreateWithFlags(&P->last_run, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -205,7 +225,7 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
     return api_hip_fail(e, "batch plan");
   }
   P->dev = device_view(P->work, (const char*)P->desc, P->o_sims, P->o_terms, P->o_reduce,
-                       P->o_apply);
+                       P->o_apply, P->o_chain);
   const int wps = opt.waves_per_simd ? opt.waves_per_simd : 2;
   const int64_t blocks = (int64_t)cu * wps;  // 256-thread blocks: one wave per SIMD each
   P->grid_blocks = (int)std::max<int64_t>(1, std::min(blocks, (P->work.n_items + 3) / 4));
@@ -251,7 +271,7 @@ mss_status mss_batch_layout(const mss_batch_plan* P, int64_t* psi0_off, int64_t*
 
 mss_status mss_batch_workspace_size(const mss_batch_plan* P, int32_t store_u, size_t* bytes) {
   if (!P || !bytes) return api_fail(MSS_E_INVALID, "plan and bytes are required");
-  *bytes = scan_base(P, store_u != 0) + P->scan_bytes;
+  *bytes = ws_need(P, store_u != 0);
   return api_ok();
 }
 
@@ -287,15 +307,13 @@ mss_status mss_batch_run(mss_batch_plan* P, const double* params, const double* 
       P->exec = nullptr;
     }
     hipFunction_t fn = nullptr;
-    if ((s = user_function(P, &fn)) != MSS_OK) return s;
+    if ((s = user_function(P, &fn, P->work.chained)) != MSS_OK) return s;
     hipError_t e = hipSuccess;
     if (!P->capture_stream) e = hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking);
     hipGraph_t g = nullptr;
     if (e == hipSuccess) e = hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-      hipError_t el = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks,
-                                            P->capture_stream, fn);
-      if (el == hipSuccess) el = launch_work_scan(P->dev, P->capture_stream);
+      hipError_t el = launch_batch(P, true, true, ws, fn, P->capture_stream);
       hipError_t e2 = hipStreamEndCapture(P->capture_stream, &g);
       e = el != hipSuccess ? el : e2;
     }
@@ -313,6 +331,8 @@ mss_status mss_batch_run(mss_batch_plan* P, const double* params, const double* 
 mss_status mss_batch_integrate(mss_batch_plan* P, const double* params, double* U, void* ws,
                                size_t ws_bytes, void* stream) {
   if (!P) return api_fail(MSS_E_INVALID, "plan is NULL");
+  if (P->work.chained && !U)
+    return api_fail(MSS_E_INVALID, "a chained plan keeps no operators: mss_batch_integrate needs U");
   mss_status s = check_ws(P, U != nullptr, ws, ws_bytes);
   if (s != MSS_OK) return s;
   // the integrator reads no states: keep whatever state pointers are bound
@@ -328,6 +348,10 @@ mss_status mss_batch_propagate(mss_batch_plan* P, const double* psi0, double* ps
                                double* psi_final, const double* U, void* ws, size_t ws_bytes,
                                void* stream) {
   if (!P) return api_fail(MSS_E_INVALID, "plan is NULL");
+  if (P->work.chained)
+    return api_fail(MSS_E_UNSUPPORTED,
+                    "a chained plan forms its states in mss_batch_run (create the plan with "
+                    "chained = 0 for a separate scan)");
   if (!psi0 || !psi) return api_fail(MSS_E_INVALID, "psi0 and psi are required");
   mss_status s = check_ws(P, U != nullptr, ws, ws_bytes);
   if (s != MSS_OK) return s;

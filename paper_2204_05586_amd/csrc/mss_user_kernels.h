@@ -48,3 +48,8 @@ extern "C" __global__ void __launch_bounds__(256) mss_user_work_integrate(
     const mss::IntegrateWorkArgs A) {
   mss::work_integrate_loop(A, MssUserSource{});
 }
+
+extern "C" __global__ void __launch_bounds__(256) mss_user_work_chained(
+    const mss::IntegrateWorkArgs A) {
+  mss::chained_integrate_loop(A, MssUserSource{});
+}

@@ -27,6 +27,13 @@ size_t scan_scratch_bytes(int N, int64_t K, int tile = kScanTile);
 // packs everything for one upload.
 struct WorkSet {
   int scan_e = kScanPerLane;  // operators per lane in the scan: 2, 4 or 8
+  // chained runs (states formed in the integrator's launch): every sequence
+  // is integrated whole (k_first = 0, k_count = K_total) and finalize()
+  // builds the interleaved item order (IntegrateWorkArgs)
+  bool chained = false;
+  std::vector<int32_t> order;                    // sequences by decreasing item count
+  std::vector<int64_t> group_item0, group_round0;
+  std::vector<int32_t> group_count;
   std::vector<SimDesc> sims;
   std::vector<mss_term> terms;
   int64_t n_items = 0;
@@ -42,7 +49,7 @@ struct WorkSet {
   // Bytes of the packed descriptor image and the image itself.
   size_t packed_bytes() const;
   void pack(char* dst, size_t* o_sims, size_t* o_terms, std::vector<size_t>* o_reduce,
-            std::vector<size_t>* o_apply) const;
+            std::vector<size_t>* o_apply, size_t* o_chain = nullptr) const;
 
  private:
   const mss_term* last_terms_ = nullptr;
@@ -59,10 +66,17 @@ struct DevWork {
   int64_t n_items = 0;
   int n_levels = 0;
   int scan_e = kScanPerLane;
+  // chained runs
+  int32_t n_groups = 0;
+  const int64_t* group_item0 = nullptr;
+  const int64_t* group_round0 = nullptr;
+  const int32_t* group_count = nullptr;
+  const int32_t* order = nullptr;
 };
 
 DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_t o_terms,
-                    const std::vector<size_t>& o_reduce, const std::vector<size_t>& o_apply);
+                    const std::vector<size_t>& o_reduce, const std::vector<size_t>& o_apply,
+                    size_t o_chain = 0);
 
 // Enqueue the integrator (counter cleared by a kernel first, unless the
 // caller's stream has already zeroed it: counter_zeroed) over every range of
@@ -74,5 +88,14 @@ hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, 
                                  bool counter_zeroed = false);
 // Enqueue the scan of every scanning sequence (reduce up, apply down).
 hipError_t launch_work_scan(const DevWork& w, hipStream_t st);
+
+// Enqueue a chained run of a chained work set: a reset kernel (item counter
+// to 0, call number + 1) and the persistent integrator that also forms the
+// states.  ws starts with a ChainSync block followed by one ChainSlot per
+// sequence (chain_workspace_bytes).  user_fn: the chained work integrator
+// of a user sampler's module, or null for the field-program kernel.
+size_t chain_workspace_bytes(int32_t n_sims);
+hipError_t launch_work_chained(const DevWork& w, void* ws, int grid_blocks, hipStream_t st,
+                               hipFunction_t user_fn = nullptr);
 
 }  // namespace mss

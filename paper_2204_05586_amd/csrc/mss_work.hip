@@ -75,6 +75,19 @@ __global__ void __launch_bounds__(256) work_integrate_kernel(const IntegrateWork
   work_integrate_loop(A, TableSource{});
 }
 
+__global__ void __launch_bounds__(256) work_chained_kernel(const IntegrateWorkArgs A) {
+  chained_integrate_loop(A, TableSource{});
+}
+
+// Before a chained run: item counter to 0, next call number.  A kernel
+// rather than a memset, so a captured graph replays it as such.
+__global__ void chain_reset_kernel(ChainSync* s) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    s->counter = 0ull;
+    s->epoch = s->epoch + 1ull;
+  }
+}
+
 // Element count of a sequence at a scan level and the start of that level's
 // arrays in the sequence's scratch (levels >= 1).
 template <int N, int E>
@@ -190,6 +203,33 @@ void WorkSet::finalize() {
     n_levels = std::max(n_levels, d.top);
   }
   n_items = item;
+  if (chained) {
+    // item counts per sequence, sequences by decreasing count; walking from
+    // the shortest up, each new count starts a group of rounds in which
+    // exactly the sequences before it (in `order`) and itself take part
+    std::vector<int64_t> cnt(n);
+    for (int i = 0; i < n; ++i) {
+      const int64_t per = 64 >> sims[i].slices_log2;
+      cnt[i] = (sims[i].k_count + per - 1) / per;
+    }
+    order.resize(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
+    group_item0.clear();
+    group_round0.clear();
+    group_count.clear();
+    int64_t round = 0, at = 0;
+    for (int j = n - 1; j >= 0; --j) {
+      const int64_t m = cnt[order[j]];
+      if (m <= round) continue;
+      group_item0.push_back(at);
+      group_round0.push_back(round);
+      group_count.push_back(j + 1);
+      at += (m - round) * (j + 1);
+      round = m;
+    }
+  }
   reduce_tiles.assign(n_levels, std::vector<int64_t>(n + 1, 0));
   apply_tiles.assign(n_levels + 1, std::vector<int64_t>(n + 1, 0));
   const int tile = 64 * scan_e;
@@ -206,14 +246,22 @@ void WorkSet::finalize() {
   }
 }
 
+// chained tables: group_item0, group_round0, group_count, order
+static size_t chain_table_bytes(size_t groups, size_t sims) {
+  return 2 * a256(std::max<size_t>(1, groups) * sizeof(int64_t)) +
+         a256(std::max<size_t>(1, groups) * sizeof(int32_t)) +
+         a256(std::max<size_t>(1, sims) * sizeof(int32_t));
+}
+
 size_t WorkSet::packed_bytes() const {
   size_t b = a256(sims.size() * sizeof(SimDesc)) + a256(std::max<size_t>(1, terms.size()) * sizeof(mss_term));
   b += (reduce_tiles.size() + apply_tiles.size()) * a256((sims.size() + 1) * sizeof(int64_t));
+  if (chained) b += chain_table_bytes(group_item0.size(), sims.size());
   return b;
 }
 
 void WorkSet::pack(char* dst, size_t* o_sims, size_t* o_terms, std::vector<size_t>* o_reduce,
-                   std::vector<size_t>* o_apply) const {
+                   std::vector<size_t>* o_apply, size_t* o_chain) const {
   size_t off = 0;
   *o_sims = off;
   memcpy(dst + off, sims.data(), sims.size() * sizeof(SimDesc));
@@ -234,11 +282,35 @@ void WorkSet::pack(char* dst, size_t* o_sims, size_t* o_terms, std::vector<size_
     memcpy(dst + off, t.data(), t.size() * sizeof(int64_t));
     off += tb;
   }
+  if (o_chain) *o_chain = off;
+  if (chained) {
+    const size_t g = group_item0.size();
+    memcpy(dst + off, group_item0.data(), g * sizeof(int64_t));
+    off += a256(std::max<size_t>(1, g) * sizeof(int64_t));
+    memcpy(dst + off, group_round0.data(), g * sizeof(int64_t));
+    off += a256(std::max<size_t>(1, g) * sizeof(int64_t));
+    memcpy(dst + off, group_count.data(), g * sizeof(int32_t));
+    off += a256(std::max<size_t>(1, g) * sizeof(int32_t));
+    memcpy(dst + off, order.data(), order.size() * sizeof(int32_t));
+  }
 }
 
 DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_t o_terms,
-                    const std::vector<size_t>& o_reduce, const std::vector<size_t>& o_apply) {
+                    const std::vector<size_t>& o_reduce, const std::vector<size_t>& o_apply,
+                    size_t o_chain) {
   DevWork d;
+  if (w.chained) {
+    const size_t g = w.group_item0.size();
+    d.n_groups = (int32_t)g;
+    size_t off = o_chain;
+    d.group_item0 = (const int64_t*)(dev_base + off);
+    off += a256(std::max<size_t>(1, g) * sizeof(int64_t));
+    d.group_round0 = (const int64_t*)(dev_base + off);
+    off += a256(std::max<size_t>(1, g) * sizeof(int64_t));
+    d.group_count = (const int32_t*)(dev_base + off);
+    off += a256(std::max<size_t>(1, g) * sizeof(int32_t));
+    d.order = (const int32_t*)(dev_base + off);
+  }
   d.sims = (const SimDesc*)(dev_base + o_sims);
   d.terms = (const mss_term*)(dev_base + o_terms);
   d.n_sims = (int32_t)w.sims.size();
@@ -269,6 +341,34 @@ hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, 
                                  nullptr);
   }
   hipLaunchKernelGGL(work_integrate_kernel, dim3(grid_blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t chain_workspace_bytes(int32_t n_sims) {
+  return sizeof(ChainSync) + a256((size_t)std::max(1, n_sims) * sizeof(ChainSlot));
+}
+
+hipError_t launch_work_chained(const DevWork& w, void* ws, int grid_blocks, hipStream_t st,
+                               hipFunction_t user_fn) {
+  if (w.n_items == 0) return hipSuccess;
+  ChainSync* sync = (ChainSync*)ws;
+  hipLaunchKernelGGL(chain_reset_kernel, dim3(1), dim3(64), 0, st, sync);
+  IntegrateWorkArgs a{w.sims, w.terms, &sync->counter, w.n_items, w.n_sims};
+  a.n_groups = w.n_groups;
+  a.group_item0 = w.group_item0;
+  a.group_round0 = w.group_round0;
+  a.group_count = w.group_count;
+  a.order = w.order;
+  a.slots = (ChainSlot*)((char*)ws + sizeof(ChainSync));
+  a.sync = sync;
+  if (user_fn) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* args[] = {&a};
+    return hipModuleLaunchKernel(user_fn, (unsigned)grid_blocks, 1, 1, 256, 1, 1, 0, st, args,
+                                 nullptr);
+  }
+  hipLaunchKernelGGL(work_chained_kernel, dim3(grid_blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

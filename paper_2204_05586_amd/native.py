@@ -87,7 +87,7 @@ class Launch(C.Structure):
 class BatchOptions(C.Structure):
     _fields_ = [("slices_spin_half", C.c_int32), ("slices_spin_one", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("use_graph", C.c_int32),
-                ("scan_per_lane", C.c_int32)]
+                ("scan_per_lane", C.c_int32), ("chained", C.c_int32)]
 
 
 class ServerOptions(C.Structure):
@@ -482,11 +482,13 @@ class BatchPlan:
     differ), compile that field program into its own integrator
     (``Sampler.for_terms``, bit-for-bit the interpreter's operators) and run
     the batch with it; otherwise the terms are interpreted.  The plan owns
-    that sampler; ``specialized`` tells which happened."""
+    that sampler; ``specialized`` tells which happened.
+    chained: ``run`` forms the states inside the integrator's launch (no
+    operator buffer, no scan; see mss_batch_options.chained)."""
 
     def __init__(self, problems, slices_spin_half=0, slices_spin_one=0, waves_per_simd=0,
                  use_graph=False, scan_per_lane=0, sampler: "Optional[Sampler]" = None,
-                 specialize: bool = False):
+                 specialize: bool = False, chained: bool = False):
         self.problems = list(problems)
         self._own_sampler = None
         self.specialized = False
@@ -508,11 +510,12 @@ class BatchPlan:
             self.param_off[:n] = np.concatenate([[0], np.cumsum(counts)[:-1]])
         self.n_params_total = int(counts.sum())
         opt = BatchOptions(int(slices_spin_half), int(slices_spin_one), int(waves_per_simd),
-                           int(bool(use_graph)), int(scan_per_lane))
+                           int(bool(use_graph)), int(scan_per_lane), int(bool(chained)))
         self.options = {"slices_spin_half": int(slices_spin_half),
                         "slices_spin_one": int(slices_spin_one),
                         "waves_per_simd": int(waves_per_simd), "use_graph": bool(use_graph),
-                        "scan_per_lane": int(scan_per_lane)}
+                        "scan_per_lane": int(scan_per_lane), "chained": bool(chained)}
+        self.chained = bool(chained)
         h = C.c_void_p()
         offp = self.param_off.ctypes.data_as(C.POINTER(C.c_int64))
         self.sampler = sampler
