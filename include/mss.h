@@ -317,7 +317,7 @@ typedef struct mss_batch_options {
                                registers and passes its leaving state to the next item of its
                                simulation, items being taken round by round across the
                                simulations; no operator buffer and no scan (U, when given, is
-                               still written).  The workspace is then a 256-byte head plus 64
+                               still written).  The workspace is then a 256-byte head plus 128
                                bytes per simulation, mss_batch_propagate is not available and
                                mss_batch_integrate needs U.  0: separate scan. */
 } mss_batch_options;
@@ -375,6 +375,21 @@ mss_status mss_batch_propagate(mss_batch_plan* plan, const double* psi0, double*
 
 /* Free the plan (its graph, stream and descriptors). */
 void mss_batch_plan_destroy(mss_batch_plan* plan);
+
+/* A whole batch in one call, the paper's evaluate() over many simulations
+ * (Sec. "Compilation of integrator"): plans a chained batch with default
+ * options, runs it on `stream`, waits for it and frees what it allocated
+ * (descriptors and a workspace of 256 + 128 n bytes).  problems / param_off
+ * as mss_batch_plan_create; params, psi0, psi, psi_final (optional) and U
+ * (optional) are device arrays in the packed layout of mss_batch_layout,
+ * which follows from the problems alone: simulation i's psi0 / psi_final at
+ * the sum of N_j over j < i, its states at the sum of K_j N_j, its
+ * operators at the sum of K_j N_j^2 (complex units).  Synchronous: returns
+ * once the outputs are written.  Errors as the plan calls, plus
+ * MSS_E_NOMEM when the workspace cannot be allocated. */
+mss_status mss_solve_batch(int32_t n, const mss_problem* problems, const int64_t* param_off,
+                           const double* params, const double* psi0, double* psi,
+                           double* psi_final, double* U, void* stream);
 
 /* ---- serving ------------------------------------------------------------
  * Continuous batching of simulation requests (mixed spin and length) on the
@@ -494,6 +509,17 @@ mss_status mss_adjoint_run(mss_adjoint_plan* plan, const double* params, const d
                            double* loss, double* grad, double* psi_final, void* ws,
                            size_t ws_bytes, void* stream);
 void mss_adjoint_plan_destroy(mss_adjoint_plan* plan);
+
+/* Losses and gradients in one call: plans as mss_adjoint_plan_create, runs
+ * mss_adjoint_run on `stream` with a workspace it allocates, waits and
+ * frees everything.  Buffers as mss_adjoint_run (grad has
+ * mss_adjoint_param_count entries: the largest param_off[i] + n_params_i).
+ * Synchronous.  Errors as the plan calls, plus MSS_E_NOMEM when the
+ * workspace cannot be allocated. */
+mss_status mss_adjoint_population(int32_t n, const mss_problem* problems,
+                                  const int64_t* param_off, int32_t level_m,
+                                  const double* params, const double* psi0, double* loss,
+                                  double* grad, double* psi_final, void* stream);
 
 #ifdef __cplusplus
 }

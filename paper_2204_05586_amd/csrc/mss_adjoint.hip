@@ -880,4 +880,27 @@ mss_status mss_adjoint_run(mss_adjoint_plan* P, const double* params, const doub
 
 void mss_adjoint_plan_destroy(mss_adjoint_plan* P) { release(P); }
 
+mss_status mss_adjoint_population(int32_t n, const mss_problem* problems,
+                                  const int64_t* param_off, int32_t level_m,
+                                  const double* params, const double* psi0, double* loss,
+                                  double* grad, double* psi_final, void* stream) {
+  mss_adjoint_plan* P = nullptr;
+  mss_status s = mss_adjoint_plan_create(n, problems, param_off, level_m, &P);
+  if (s != MSS_OK) return s;
+  void* ws = nullptr;
+  hipError_t e = hipMalloc(&ws, std::max<size_t>(P->ws_bytes, 256));
+  if (e != hipSuccess)
+    s = e == hipErrorOutOfMemory ? api_fail(MSS_E_NOMEM, "workspace allocation failed")
+                                 : api_hip_fail(e, "workspace allocation");
+  if (s == MSS_OK)
+    s = mss_adjoint_run(P, params, psi0, loss, grad, psi_final, ws, P->ws_bytes, stream);
+  if (s == MSS_OK) {
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) s = api_hip_fail(e, "adjoint wait");
+  }
+  if (ws) (void)hipFree(ws);
+  release(P);
+  return s == MSS_OK ? api_ok() : s;
+}
+
 }  // extern "C"

@@ -16,6 +16,7 @@ using namespace mss;
 
 struct mss_batch_plan {
   int32_t n = 0;
+  bool needs_params = false;  // some simulation reads parameter slots
   WorkSet work;
   std::vector<int64_t> psi0_off, state_off, op_off, param_off;
   std::vector<size_t> scan_off;  // byte offsets of each simulation's scan scratch
@@ -206,6 +207,7 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
     P->state_off[i + 1] = P->state_off[i] + q.n_samples * N;
     P->op_off[i + 1] = P->op_off[i] + q.n_samples * N * N;
     P->param_off[i] = q.n_params > 0 ? param_off[i] : 0;
+    if (q.n_params > 0) P->needs_params = true;
     P->scan_off[i] = scan;
     if (!P->work.chained) scan += scan_scratch_bytes(N, q.n_samples, 64 * scan_e);
     int S = S_class[q.spin_twice - 1];
@@ -213,6 +215,16 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
     P->work.add(q, api_ilog2(S), 0, q.n_samples, !P->work.chained);
   }
   P->work.finalize();
+  if (P->work.chained) {
+    // unit tags are unit + 1 in 32 bits
+    for (int i = 0; i < n; ++i) {
+      const int64_t per = 64 >> P->work.sims[i].slices_log2;
+      if ((problems[i].n_samples + per - 1) / per >= ((int64_t)1 << 31)) {
+        release(P);
+        return api_fail(MSS_E_UNSUPPORTED, "simulation %d is too long for a chained plan", i);
+      }
+    }
+  }
   P->scan_bytes = scan;
   P->op_total = P->op_off[n];
   P->image.resize(P->work.packed_bytes());
@@ -291,6 +303,8 @@ mss_status mss_batch_run(mss_batch_plan* P, const double* params, const double* 
                          double* psi_final, double* U, void* ws, size_t ws_bytes, void* stream) {
   if (!P) return api_fail(MSS_E_INVALID, "plan is NULL");
   if (!psi0 || !psi) return api_fail(MSS_E_INVALID, "psi0 and psi are required");
+  if (P->needs_params && !params)
+    return api_fail(MSS_E_INVALID, "params is NULL but the batch has parameterised simulations");
   mss_status s = check_ws(P, U != nullptr, ws, ws_bytes);
   if (s != MSS_OK) return s;
   if ((s = bind(P, params, psi0, psi, psi_final, U, ws)) != MSS_OK) return s;
@@ -333,6 +347,8 @@ mss_status mss_batch_integrate(mss_batch_plan* P, const double* params, double* 
   if (!P) return api_fail(MSS_E_INVALID, "plan is NULL");
   if (P->work.chained && !U)
     return api_fail(MSS_E_INVALID, "a chained plan keeps no operators: mss_batch_integrate needs U");
+  if (P->needs_params && !params)
+    return api_fail(MSS_E_INVALID, "params is NULL but the batch has parameterised simulations");
   mss_status s = check_ws(P, U != nullptr, ws, ws_bytes);
   if (s != MSS_OK) return s;
   // the integrator reads no states: keep whatever state pointers are bound
@@ -362,5 +378,34 @@ mss_status mss_batch_propagate(mss_batch_plan* P, const double* psi0, double* ps
 }
 
 void mss_batch_plan_destroy(mss_batch_plan* P) { release(P); }
+
+mss_status mss_solve_batch(int32_t n, const mss_problem* problems, const int64_t* param_off,
+                           const double* params, const double* psi0, double* psi,
+                           double* psi_final, double* U, void* stream) {
+  if (!psi0 || !psi) return api_fail(MSS_E_INVALID, "psi0 and psi are required");
+  mss_batch_options opt{};
+  opt.chained = 1;
+  mss_batch_plan* P = nullptr;
+  mss_status s = create_plan(n, problems, param_off, &opt, nullptr, &P);
+  if (s != MSS_OK) return s;
+  if (P->needs_params && !params)
+    s = api_fail(MSS_E_INVALID, "params is NULL but the batch has parameterised simulations");
+  const size_t bytes = ws_need(P, U != nullptr);
+  void* ws = nullptr;
+  if (s == MSS_OK) {
+    hipError_t e = hipMalloc(&ws, bytes);
+    if (e != hipSuccess)
+      s = e == hipErrorOutOfMemory ? api_fail(MSS_E_NOMEM, "workspace allocation failed")
+                                   : api_hip_fail(e, "workspace allocation");
+  }
+  if (s == MSS_OK) s = mss_batch_run(P, params, psi0, psi, psi_final, U, ws, bytes, stream);
+  if (s == MSS_OK) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) s = api_hip_fail(e, "batch wait");
+  }
+  if (ws) (void)hipFree(ws);
+  release(P);
+  return s == MSS_OK ? api_ok() : s;
+}
 
 }  // extern "C"

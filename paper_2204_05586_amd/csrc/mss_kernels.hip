@@ -114,21 +114,39 @@ __device__ __forceinline__ unsigned long long call_tag(unsigned long long c) {
   return c;
 }
 
-__device__ __forceinline__ unsigned long long load_acquire(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void store_release(unsigned long long* p, unsigned long long v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Every lane of the wave polls until *p == want; false when the bound ran out.
-__device__ __forceinline__ bool wait_equal(const unsigned long long* p, unsigned long long want) {
+// The current value of a word, read by an atomic compare-and-swap of 0
+// with 0 (it writes only a 0 that is already there): a real read-modify-
+// write at agent scope, which takes effect at the device's coherence point,
+// whereas a plain or relaxed load (and an idempotent fetch-add, which the
+// compiler turns into one) can keep returning a line the reading XCD's L2
+// holds.
+__device__ __forceinline__ unsigned long long coherent_read(unsigned long long* p) {
+  unsigned long long v = 0ull;
+  __hip_atomic_compare_exchange_strong(p, &v, 0ull, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
+
+// Every lane of the wave polls (coherent_read) until *p == want, then one
+// acquire fence makes what was written before the tag visible; false when
+// the bound ran out.
+__device__ __forceinline__ bool wait_equal(unsigned long long* p, unsigned long long want) {
   const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+  bool ok = true;
   for (;;) {
-    if (__all(load_acquire(p) == want)) return true;
-    if (__builtin_amdgcn_s_memrealtime() - t0 > kScanWaitTicks) return false;
+    if (__all(coherent_read(p) == want)) break;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > kScanWaitTicks) {
+      ok = false;
+      break;
+    }
     __builtin_amdgcn_s_sleep(2);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
 }
 
 struct OnePassArgs {
@@ -167,7 +185,7 @@ __global__ void __launch_bounds__(256) scan_one_pass_kernel(const OnePassArgs A)
     bool ok = true;
     for (int64_t base = (int64_t)wave * 64; base < A.n1; base += 256) {
       const int64_t idx = base + lane;
-      const unsigned long long* t = A.tags + (idx < A.n1 ? idx : A.n1 - 1);
+      unsigned long long* t = A.tags + (idx < A.n1 ? idx : A.n1 - 1);
       ok = ok && wait_equal(t, tag);
     }
     if (!ok && lane == 0) A.sync->failed = tag;

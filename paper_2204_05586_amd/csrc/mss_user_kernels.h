@@ -49,7 +49,7 @@ extern "C" __global__ void __launch_bounds__(256) mss_user_work_integrate(
   mss::work_integrate_loop(A, MssUserSource{});
 }
 
-extern "C" __global__ void __launch_bounds__(256) mss_user_work_chained(
+extern "C" __global__ void __launch_bounds__(256, 2) mss_user_work_chained(
     const mss::IntegrateWorkArgs A) {
   mss::chained_integrate_loop(A, MssUserSource{});
 }

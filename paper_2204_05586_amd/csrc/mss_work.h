@@ -31,7 +31,8 @@ struct WorkSet {
   // is integrated whole (k_first = 0, k_count = K_total) and finalize()
   // builds the interleaved item order (IntegrateWorkArgs)
   bool chained = false;
-  std::vector<int32_t> order;                    // sequences by decreasing item count
+  int64_t n_units = 0;                           // chained units (64 / S intervals each)
+  std::vector<int32_t> order;                    // sequences by decreasing unit count
   std::vector<int64_t> group_item0, group_round0;
   std::vector<int32_t> group_count;
   std::vector<SimDesc> sims;
@@ -67,6 +68,7 @@ struct DevWork {
   int n_levels = 0;
   int scan_e = kScanPerLane;
   // chained runs
+  int64_t n_units = 0;
   int32_t n_groups = 0;
   const int64_t* group_item0 = nullptr;
   const int64_t* group_round0 = nullptr;

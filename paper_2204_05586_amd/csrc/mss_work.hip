@@ -75,17 +75,21 @@ __global__ void __launch_bounds__(256) work_integrate_kernel(const IntegrateWork
   work_integrate_loop(A, TableSource{});
 }
 
-__global__ void __launch_bounds__(256) work_chained_kernel(const IntegrateWorkArgs A) {
+__global__ void __launch_bounds__(256, 2) work_chained_kernel(const IntegrateWorkArgs A) {
   chained_integrate_loop(A, TableSource{});
 }
 
-// Before a chained run: item counter to 0, next call number.  A kernel
-// rather than a memset, so a captured graph replays it as such.
-__global__ void chain_reset_kernel(ChainSync* s) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    s->counter = 0ull;
-    s->epoch = s->epoch + 1ull;
+// Before a chained run: unit counter and failure word to 0, every slot
+// word to 0 (tag 0, which no unit writes).  Atomic stores, like every
+// other access to these words; a kernel rather than a memset, so a captured
+// graph replays it as such.
+__global__ void chain_reset_kernel(ChainSync* s, unsigned long long* words, int64_t n_words) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    __hip_atomic_store(&s->counter, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&s->failed, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if (i < n_words) __hip_atomic_store(words + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Element count of a sequence at a scan level and the start of that level's
@@ -204,13 +208,16 @@ void WorkSet::finalize() {
   }
   n_items = item;
   if (chained) {
-    // item counts per sequence, sequences by decreasing count; walking from
-    // the shortest up, each new count starts a group of rounds in which
-    // exactly the sequences before it (in `order`) and itself take part
+    // unit counts per sequence (64 / S intervals each), sequences by
+    // decreasing count; walking from the shortest up, each new count starts
+    // a group of rounds in which exactly the sequences before it (in
+    // `order`) and itself take part
     std::vector<int64_t> cnt(n);
+    n_units = 0;
     for (int i = 0; i < n; ++i) {
       const int64_t per = 64 >> sims[i].slices_log2;
       cnt[i] = (sims[i].k_count + per - 1) / per;
+      n_units += cnt[i];
     }
     order.resize(n);
     for (int i = 0; i < n; ++i) order[i] = i;
@@ -317,6 +324,7 @@ DevWork device_view(const WorkSet& w, const char* dev_base, size_t o_sims, size_
   d.n_items = w.n_items;
   d.n_levels = w.n_levels;
   d.scan_e = w.scan_e;
+  d.n_units = w.n_units;
   for (size_t l = 0; l < o_reduce.size(); ++l) {
     d.reduce_tiles.push_back((const int64_t*)(dev_base + o_reduce[l]));
     d.reduce_total.push_back(w.reduce_tiles[l].back());
@@ -350,16 +358,19 @@ size_t chain_workspace_bytes(int32_t n_sims) {
 
 hipError_t launch_work_chained(const DevWork& w, void* ws, int grid_blocks, hipStream_t st,
                                hipFunction_t user_fn) {
-  if (w.n_items == 0) return hipSuccess;
+  if (w.n_units == 0) return hipSuccess;
   ChainSync* sync = (ChainSync*)ws;
-  hipLaunchKernelGGL(chain_reset_kernel, dim3(1), dim3(64), 0, st, sync);
-  IntegrateWorkArgs a{w.sims, w.terms, &sync->counter, w.n_items, w.n_sims};
+  const int64_t n_words = (int64_t)w.n_sims * (sizeof(ChainSlot) / sizeof(unsigned long long));
+  ChainSlot* slots = (ChainSlot*)((char*)ws + sizeof(ChainSync));
+  hipLaunchKernelGGL(chain_reset_kernel, dim3((unsigned)((n_words + 255) / 256)), dim3(256), 0, st,
+                     sync, (unsigned long long*)slots, n_words);
+  IntegrateWorkArgs a{w.sims, w.terms, &sync->counter, w.n_units, w.n_sims};
   a.n_groups = w.n_groups;
   a.group_item0 = w.group_item0;
   a.group_round0 = w.group_round0;
   a.group_count = w.group_count;
   a.order = w.order;
-  a.slots = (ChainSlot*)((char*)ws + sizeof(ChainSync));
+  a.slots = slots;
   a.sync = sync;
   if (user_fn) {
     hipError_t e = hipGetLastError();

@@ -26,24 +26,30 @@ struct SimDesc {
 };
 
 // Chained runs: the states are formed inside the integrator's launch.  Each
-// simulation has one slot through which its work items pass the state on:
-// item r of the simulation writes the state leaving its last interval and
-// then its tag, chain_tag(call, r); item r + 1 waits for that tag.
+// simulation has one slot through which its work units pass the state on.
+// The state (N complex = 4N 32-bit halves) travels in 4N 64-bit words, each
+// holding one half in its low 32 bits and the tag r + 1 of the unit r that
+// wrote it in its high 32 bits.  Words are written (exchange) and read
+// (compare-and-swap, chain_read) only by atomic read-modify-write
+// operations at agent scope, which take effect at the device's coherence
+// point whichever XCD issues them, so a reader sees each word either old or
+// new and needs no cache maintenance or fence (a plain or relaxed load, by
+// contrast, can keep returning a line its XCD's L2 holds): once all
+// 4N words carry the tag it waits for, they hold that unit's state.  A
+// reset kernel zeroes every slot before each run, so a word can only hold
+// 0 or the tag of an earlier unit of the same run.
 struct ChainSlot {
-  unsigned long long tag;
-  unsigned long long pad;
-  double psi[6];  // N complex
+  unsigned long long w[16];  // 4N words used
 };
-static_assert(sizeof(ChainSlot) == 64, "one chain slot is 64 bytes");
+static_assert(sizeof(ChainSlot) == 128, "one chain slot is 128 bytes");
 
-// Head of a chained run's workspace: the item counter, the number of the
-// last call (incremented by the reset kernel before each run) and the tag of
-// a call whose bounded wait ran out (0 if none ever did).
+// Head of a chained run's workspace: the unit counter and the tag of a
+// wait that ran out in this run (0 if none did), both cleared by the reset
+// kernel.
 struct ChainSync {
   unsigned long long counter;
-  unsigned long long epoch;
   unsigned long long failed;
-  unsigned long long pad[29];
+  unsigned long long pad[30];
 };
 static_assert(sizeof(ChainSync) == 256, "the chain head is one 256-byte block");
 
@@ -53,12 +59,13 @@ struct IntegrateWorkArgs {
   unsigned long long* counter;
   int64_t n_items;
   int32_t n_sims;
-  // chained runs only: the interleaved item order and the chain slots.
-  // Items go round by round (item r of every simulation that has one, then
-  // item r + 1, ...), simulations within a round by decreasing item count,
-  // so a round's simulations are a prefix of `order`.  Rounds with the same
-  // simulation count form a group: group g starts at item group_item0[g]
-  // and round group_round0[g] and holds group_count[g] simulations per round.
+  // chained runs only (n_items then counts units of 64 / S intervals): the
+  // interleaved unit order and the chain slots.  Units go round by round
+  // (unit r of every simulation that has one, then unit r + 1, ...),
+  // simulations within a round by decreasing unit count, so a round's
+  // simulations are a prefix of `order`.  Rounds with the same simulation
+  // count form a group: group g starts at unit group_item0[g] and round
+  // group_round0[g] and holds group_count[g] simulations per round.
   int32_t n_groups;
   const int64_t* group_item0;   // [n_groups]
   const int64_t* group_round0;  // [n_groups]
@@ -104,54 +111,112 @@ __device__ __forceinline__ void work_item(const IntegrateWorkArgs& A, const SimD
 // ---------------------------------------------------------------------------
 // chained runs
 // ---------------------------------------------------------------------------
-// The finalizer of SplitMix64 (Steele, Lea and Flood, 2014): a bijection of
-// 64-bit words.  The tag of item r in call c is the image of c 2^40 + r, so
-// no two (call, item) pairs share a tag (r < 2^40, calls counted modulo
-// 2^24) and whatever a slot held before matches only by a 2^-64 chance.
-__device__ __forceinline__ unsigned long long chain_tag(unsigned long long call, int64_t r) {
-  unsigned long long c = (call << 40) | ((unsigned long long)r & ((1ull << 40) - 1));
-  c ^= c >> 30;
-  c *= 0xbf58476d1ce4e5b9ull;
-  c ^= c >> 27;
-  c *= 0x94d049bb133111ebull;
-  c ^= c >> 31;
-  return c;
-}
-
 // Upper bound of one wait, in ticks of the 100 MHz real-time counter (10 s,
-// far beyond any real wait: an item waits at most for the items dequeued
+// far beyond any real wait: a unit waits at most for the units dequeued
 // before it).
 constexpr unsigned long long kChainWaitTicks = 1000000000ull;
 
-// Every lane polls until *p == want; false when the bound ran out.
-__device__ __forceinline__ bool chain_wait(const unsigned long long* p, unsigned long long want) {
-  const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-  for (;;) {
-    const unsigned long long v = __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if (__all(v == want)) return true;
-    if (__builtin_amdgcn_s_memrealtime() - t0 > kChainWaitTicks) return false;
-    __builtin_amdgcn_s_sleep(2);
-  }
+// The current value of a word, read by an atomic compare-and-swap of 0
+// with 0 (it writes only a 0 that is already there): a real read-modify-
+// write, which the compiler cannot turn into a plain load (as it does with
+// an idempotent fetch-add or fetch-or) and which takes effect at the
+// device's coherence point like the work counter's increments.
+__device__ __forceinline__ unsigned long long chain_read(unsigned long long* p) {
+  unsigned long long v = 0ull;
+  __hip_atomic_compare_exchange_strong(p, &v, 0ull, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return v;
 }
 
-// One chained item: the operators of 64 / S consecutive intervals (written
-// to U when the descriptor has one), their ordered products within the
-// wave, the entering state from the item before (or psi0), and every
-// interval's entering state; the state leaving the last interval goes to
-// the slot (and to psi_final after the last interval of the simulation).
+// A wave-uniform truth value as a scalar, so that branches on it are
+// scalar branches and never split the wave's execution mask.
+__device__ __forceinline__ bool wave_uniform(bool b) {
+  return __builtin_amdgcn_readfirstlane((int)b) != 0;
+}
+
+// The state the unit with tag `tag` left in the slot (every lane receives
+// it): lanes 0 .. 4N - 1 poll one word each until all carry the tag.  The
+// loop's exits are wave-uniform.  false when the bound ran out, or a wait
+// of this run already had (then the kernel only drains its queue; the
+// states are undefined).
+template <int N>
+__device__ __forceinline__ bool chain_receive(ChainSlot* slot, unsigned tag, ChainSync* sync,
+                                              int lane, double* xr, double* xi) {
+  const bool mine = lane < 4 * N;
+  unsigned long long v = 0ull;
+  bool ok = true;
+  const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+  for (;;) {
+    if (mine) v = chain_read(&slot->w[lane]);
+    if (wave_uniform(__all(!mine || (unsigned)(v >> 32) == tag))) break;
+    // not there yet: give up at once if a wait of this run already ran out
+    unsigned long long f = 0ull;
+    if (lane == 0) f = chain_read(&sync->failed);
+    if (wave_uniform(f != 0ull)) {
+      ok = false;
+      break;
+    }
+    if (__builtin_amdgcn_s_memrealtime() - t0 > kChainWaitTicks) {
+      ok = false;
+      if (lane == 0)
+        (void)__hip_atomic_exchange(&sync->failed, (unsigned long long)tag, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  const unsigned lo32 = (unsigned)v;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const unsigned long long rl = (unsigned)__shfl((int)lo32, 4 * a, 64);
+    const unsigned long long rh = (unsigned)__shfl((int)lo32, 4 * a + 1, 64);
+    const unsigned long long il = (unsigned)__shfl((int)lo32, 4 * a + 2, 64);
+    const unsigned long long ih = (unsigned)__shfl((int)lo32, 4 * a + 3, 64);
+    xr[a] = __longlong_as_double((long long)(rl | (rh << 32)));
+    xi[a] = __longlong_as_double((long long)(il | (ih << 32)));
+  }
+  return ok;
+}
+
+// Lanes 0 .. 4N - 1 write the state (the same in every lane) into the slot
+// with tag `tag`.
+template <int N>
+__device__ __forceinline__ void chain_send(ChainSlot* slot, unsigned tag, int lane,
+                                           const double* xr, const double* xi) {
+  const int a = lane >> 2;
+  double d = 0.0;
+#pragma unroll
+  for (int b = 0; b < N; ++b)
+    if (a == b) d = (lane & 2) ? xi[b] : xr[b];
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(d);
+  const unsigned long long half = (lane & 1) ? (bits >> 32) : (bits & 0xffffffffull);
+  if (lane < 4 * N)
+    (void)__hip_atomic_exchange(&slot->w[lane], ((unsigned long long)tag << 32) | half,
+                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One chained unit: the 64 / S consecutive intervals of one simulation
+// from interval unit * 64 / S on.  The operators (written to U when the
+// descriptor has one), their ordered products within the wave, the entering
+// state (psi0 for the simulation's first unit, otherwise the state the unit
+// before left in the slot) and every interval's entering state; the state
+// leaving the unit goes to the slot, or to psi_final after the
+// simulation's last interval.  Every branch on the unit's shape is
+// wave-uniform.
 template <int N, class Source>
-__device__ __forceinline__ void chained_item(const IntegrateWorkArgs& A, const SimDesc& s,
-                                             ChainSlot* slot, int64_t local, int lane,
-                                             unsigned long long call, const Source& source) {
+__device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const SimDesc& s,
+                                             ChainSlot* slot, int64_t unit, int lane,
+                                             const Source& source) {
   const int sl = s.slices_log2;
   const int per = 64 >> sl;
-  const int jl = lane >> sl;  // interval within the item
+  const int jl = lane >> sl;  // interval within the unit
   const int slice = lane & ((1 << sl) - 1);
-  const int64_t k = local * per + jl;
+  const int64_t kb = unit * per;
+  const int64_t k = kb + jl;
   const bool active = k < s.K_total;
+  using Terms = decltype(source(A, s));
   Mat<N> P;
   double tk;
-  using Terms = decltype(source(A, s));
   bool done = false;
   if constexpr (N == 3 && has_full_basis<Terms>::value) {
     if (s.full) {
@@ -165,7 +230,7 @@ __device__ __forceinline__ void chained_item(const IntegrateWorkArgs& A, const S
                          s.frame, s.method, k, slice, sl, active, P, &tk);
   if (active && slice == 0 && s.U) store_mat<N>(s.U + (size_t)k * 2 * N * N, P);
   if (!active) set_identity<N>(P);
-  // P_j = U_j ... U_0 over the item's intervals (lanes with slice 0; the
+  // P_j = U_j ... U_0 over the unit's intervals (lanes with slice 0; the
   // other lanes compute values nobody reads)
   for (int d = 1; d < per; d <<= 1) {
     const Mat<N> o = shfl_up_mat<N>(P, d << sl);
@@ -175,19 +240,16 @@ __device__ __forceinline__ void chained_item(const IntegrateWorkArgs& A, const S
       P = t;
     }
   }
-  // entering state of the item
+  // the entering state: psi0, or what the unit before left
   double xr[N], xi[N];
-  const double* src = s.psi0;
-  if (local > 0) {
-    if (!chain_wait(&slot->tag, chain_tag(call, local - 1)) && lane == 0)
-      __hip_atomic_store(&A.sync->failed, chain_tag(call, local - 1), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    src = slot->psi;
-  }
+  if (wave_uniform(unit == 0)) {
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    xr[a] = src[2 * a];
-    xi[a] = src[2 * a + 1];
+    for (int a = 0; a < N; ++a) {
+      xr[a] = s.psi0[2 * a];
+      xi[a] = s.psi0[2 * a + 1];
+    }
+  } else {
+    (void)chain_receive<N>(slot, (unsigned)unit, A.sync, lane, xr, xi);
   }
   // y = P_j x: the state leaving interval j; the one entering it is the
   // previous interval's leaving state (x for the first)
@@ -222,40 +284,48 @@ __device__ __forceinline__ void chained_item(const IntegrateWorkArgs& A, const S
       o[2 * a] = er[a];
       o[2 * a + 1] = ei[a];
     }
-    const int64_t last = (local + 1) * per < s.K_total ? (local + 1) * per - 1 : s.K_total - 1;
-    if (k == last) {
-      if (k == s.K_total - 1) {
-        if (s.psi_final) {
-#pragma unroll
-          for (int a = 0; a < N; ++a) {
-            s.psi_final[2 * a] = yr[a];
-            s.psi_final[2 * a + 1] = yi[a];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-          slot->psi[2 * a] = yr[a];
-          slot->psi[2 * a + 1] = yi[a];
-        }
-        __hip_atomic_store(&slot->tag, chain_tag(call, local), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
   }
+  // the state leaving the unit: that of its last interval's lane
+  const int64_t n_here = s.K_total - kb < per ? s.K_total - kb : per;
+  const int last = ((int)n_here - 1) << sl;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    xr[a] = __shfl(yr[a], last, 64);
+    xi[a] = __shfl(yi[a], last, 64);
+  }
+  // Both outputs are written by lane-indexed selects under wave-uniform
+  // conditions: an if / else-if with a one-lane branch here made the
+  // compiler build the persistent loop as a divergent loop, in which a
+  // wave could reach the next dequeue without lane 0 and run a unit twice.
+  const bool more = wave_uniform(kb + per < s.K_total);
+  if (more) chain_send<N>(slot, (unsigned)(unit + 1), lane, xr, xi);
+  double f = 0.0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    if (lane == 2 * a) f = xr[a];
+    if (lane == 2 * a + 1) f = xi[a];
+  }
+  if (!more && s.psi_final && lane < 2 * N) s.psi_final[lane] = f;
 }
 
-// Persistent loop of a chained run.  An item waits only for the item of
-// its simulation one round earlier, which was taken from the counter
-// before it by a wave that is running, so every wait ends; every wave exits
-// once the queue is drained.
+// Persistent loop of a chained run.  A unit waits only for the unit of its
+// simulation one round earlier, which was taken from the counter before it
+// by a wave that is running, so every wait ends; every wave exits once the
+// queue is drained.
 template <class Source>
 __device__ __forceinline__ void chained_integrate_loop(const IntegrateWorkArgs& A,
                                                        const Source& source) {
   const int lane = threadIdx.x & 63;
-  const unsigned long long call =
-      __hip_atomic_load(&A.sync->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
+    // every lane must be here: a wave without lane 0 would take no unit from
+    // the counter and broadcast another lane's 0 instead; it stops and
+    // marks the run failed (never seen with the loop compiled uniform)
+    if (__builtin_amdgcn_read_exec() != ~0ull) {
+      if (lane == __builtin_amdgcn_readfirstlane(lane))
+        (void)__hip_atomic_exchange(&A.sync->failed, ~0ull, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
     int64_t item = 0;
     if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
     item = wave_broadcast(item);
@@ -266,13 +336,15 @@ __device__ __forceinline__ void chained_integrate_loop(const IntegrateWorkArgs& 
       if (A.group_item0[mid] <= item) lo = mid;
       else hi = mid - 1;
     }
+    // the unit's round and simulation, made explicitly wave-uniform so that
+    // every branch on the descriptor is a scalar branch
     const int64_t off = item - A.group_item0[lo];
     const int64_t cnt = A.group_count[lo];
-    const int64_t round = A.group_round0[lo] + off / cnt;
-    const int sim = A.order[off % cnt];
+    const int64_t round = wave_broadcast(A.group_round0[lo] + off / cnt);
+    const int sim = __builtin_amdgcn_readfirstlane(A.order[off % cnt]);
     const SimDesc& s = A.sims[sim];
-    if (s.spin_twice == 2) chained_item<3>(A, s, A.slots + sim, round, lane, call, source);
-    else chained_item<2>(A, s, A.slots + sim, round, lane, call, source);
+    if (s.spin_twice == 2) chained_unit<3>(A, s, A.slots + sim, round, lane, source);
+    else chained_unit<2>(A, s, A.slots + sim, round, lane, source);
   }
 }
 

@@ -35,7 +35,8 @@ EXPORTS = [
     "mss_adjoint_plan_destroy", "mss_sampler_create", "mss_sampler_log", "mss_sampler_integrate",
     "mss_sampler_solve", "mss_sampler_destroy", "mss_batch_plan_create_sampled",
     "mss_sampler_create_for_terms", "mss_sampler_min_params", "mss_propagate_spin",
-    "mss_adjoint_plan_create_compiled",
+    "mss_adjoint_plan_create_compiled", "mss_solve_batch",
+    "mss_adjoint_population",
 ]
 
 MSS_REQ_QUEUED, MSS_REQ_RUNNING, MSS_REQ_DONE, MSS_REQ_FAILED = range(4)
@@ -142,6 +143,9 @@ def lib() -> C.CDLL:
         L.mss_spin_projection.argtypes = [C.c_int32, C.c_int64, vp, vp, vp]
         L.mss_spin_projection.restype = C.c_int
         i64p = C.POINTER(C.c_int64)
+        L.mss_solve_batch.argtypes = [C.c_int32, PP, i64p, vp, vp, vp, vp, vp, vp]
+        L.mss_adjoint_population.argtypes = [C.c_int32, PP, i64p, C.c_int32, vp, vp, vp, vp,
+                                             vp, vp]
         L.mss_batch_plan_create.argtypes = [C.c_int32, PP, i64p, C.POINTER(BatchOptions),
                                             C.POINTER(vp)]
         L.mss_batch_plan_create_sampled.argtypes = [C.c_int32, PP, i64p,
@@ -197,7 +201,8 @@ def lib() -> C.CDLL:
                      "mss_sampler_integrate", "mss_sampler_solve",
                      "mss_batch_plan_create_sampled", "mss_sampler_create_for_terms",
                      "mss_propagate_spin", "mss_server_request_slices",
-                     "mss_adjoint_plan_create_compiled"):
+                     "mss_adjoint_plan_create_compiled",
+                     "mss_solve_batch", "mss_adjoint_population"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -607,6 +612,75 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def _packed_problems(problems):
+    packed = [PackedProblem(p) for p in problems]
+    arr = (Problem * max(1, len(packed)))()
+    for i, pk in enumerate(packed):
+        arr[i] = pk.c
+    counts = np.array([pk.n_params for pk in packed], dtype=np.int64)
+    off = np.zeros(max(1, len(packed)), dtype=np.int64)
+    if len(packed):
+        off[:len(packed)] = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    return packed, arr, off, int(counts.sum())
+
+
+def _host_params_psi0(problems, n_params):
+    params = (np.concatenate([np.asarray(p.params, dtype=np.float64).ravel() for p in problems])
+              if n_params else np.zeros(0))
+    psi0 = np.concatenate([np.asarray(p.psi0, dtype=np.complex128) for p in problems])
+    return params, psi0
+
+
+def solve_batch(problems, store_u: bool = False, device="cuda", stream=None) -> dict:
+    """mss_solve_batch: the whole batch in one synchronous call (a chained
+    plan made, run and freed inside).  Returns the packed device arrays
+    (psi0, psi, psi_final, U or None) and the offsets psi0_off, state_off,
+    op_off (complex units, n + 1 entries)."""
+    import torch
+    problems = list(problems)
+    packed, arr, off, n_params = _packed_problems(problems)
+    params, psi0 = _host_params_psi0(problems, n_params)
+    dims = np.array([p.spin_twice + 1 for p in problems], dtype=np.int64)
+    ks = np.array([p.n_samples for p in problems], dtype=np.int64)
+    psi0_off = np.concatenate([[0], np.cumsum(dims)])
+    state_off = np.concatenate([[0], np.cumsum(ks * dims)])
+    op_off = np.concatenate([[0], np.cumsum(ks * dims * dims)])
+    out = {"params": torch.from_numpy(params).to(device) if params.size else None,
+           "psi0": torch.from_numpy(psi0).to(device),
+           "psi": torch.empty(int(state_off[-1]), dtype=torch.complex128, device=device),
+           "psi_final": torch.empty(int(psi0_off[-1]), dtype=torch.complex128, device=device),
+           "U": (torch.empty(int(op_off[-1]), dtype=torch.complex128, device=device)
+                 if store_u else None),
+           "psi0_off": psi0_off, "state_off": state_off, "op_off": op_off}
+    check(lib().mss_solve_batch(len(problems), arr, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                _ptr(out["params"]), _ptr(out["psi0"]), _ptr(out["psi"]),
+                                _ptr(out["psi_final"]), _ptr(out["U"]), _stream(stream)))
+    return out
+
+
+def adjoint_population(problems, level_m: int, device="cuda", stream=None) -> dict:
+    """mss_adjoint_population: losses |psi_final_i[m]|^2 and their gradients
+    with respect to every parameter in one synchronous call.  Returns loss
+    [n], grad [total parameters] (simulation i's at param_off[i]),
+    psi_final and param_off."""
+    import torch
+    problems = list(problems)
+    packed, arr, off, n_params = _packed_problems(problems)
+    params, psi0 = _host_params_psi0(problems, n_params)
+    out = {"params": torch.from_numpy(params).to(device) if params.size else None,
+           "psi0": torch.from_numpy(psi0).to(device),
+           "loss": torch.empty(len(problems), dtype=torch.float64, device=device),
+           "grad": torch.empty(max(1, n_params), dtype=torch.float64, device=device),
+           "psi_final": torch.empty(psi0.size, dtype=torch.complex128, device=device),
+           "param_off": off[:len(problems)]}
+    check(lib().mss_adjoint_population(len(problems), arr,
+                                       off.ctypes.data_as(C.POINTER(C.c_int64)), int(level_m),
+                                       _ptr(out["params"]), _ptr(out["psi0"]),
+                                       _ptr(out["loss"]), _ptr(out["grad"]),
+                                       _ptr(out["psi_final"]), _stream(stream)))
+    return out
 
 
 # ---- serving ---------------------------------------------------------------

@@ -156,6 +156,20 @@ def test_propagate_spin_requires_output():
     assert st == native.MSS_E_INVALID and "spin_twice" in native.last_error()
 
 
+def test_one_shot_calls_check_before_any_device_call():
+    L = native.lib()
+    buf = (C.c_double * 64)()
+    probs = [W.spin_half_rabi(n_samples=10, n_fine=2)]
+    packed = [native.PackedProblem(p) for p in probs]
+    arr = (native.Problem * 1)(packed[0].c)
+    st = L.mss_solve_batch(1, arr, None, None, buf, None, None, None, None)
+    assert st == native.MSS_E_INVALID and "psi" in native.last_error()
+    st = L.mss_solve_batch(0, arr, None, None, buf, buf, None, None, None)
+    assert st == native.MSS_E_INVALID and "at least one" in native.last_error()
+    st = L.mss_adjoint_population(0, arr, None, 0, None, buf, buf, buf, None, None)
+    assert st == native.MSS_E_INVALID
+
+
 # ---- user field samplers (compiled at run time; needs no GPU) ---------------
 
 def test_sampler_compiles_without_gpu():
