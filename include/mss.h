@@ -189,6 +189,24 @@ mss_status mss_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
                          const double* psi0, double* psi, double* psi_final, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* mss_propagate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument and no allocation of any kind.  The
+ * scan's workspace is a static device array of 8 MiB that each GPU the
+ * library runs on holds until the process ends; its address is looked up
+ * on the first call on a device.  Every call on one GPU shares that array,
+ * so calls that overlap on one GPU (other streams, other threads) race;
+ * calls in order on one stream are fine.  Arguments, outputs and errors as
+ * mss_propagate (same kernels, same results bit for bit), plus
+ * MSS_E_INVALID, before any launch, when n_samples exceeds what the array
+ * holds: MSS_NOALLOC_MAX_SAMPLES_SPIN_ONE spin-1 or
+ * MSS_NOALLOC_MAX_SAMPLES_SPIN_HALF spin-1/2 intervals. */
+#define MSS_NOALLOC_MAX_SAMPLES_SPIN_ONE 11141120LL
+#define MSS_NOALLOC_MAX_SAMPLES_SPIN_HALF 22280192LL
+mss_status mss_propagate_noalloc(int32_t spin_twice, int64_t n_samples, const double* U,
+                                 const double* psi0, double* psi, double* psi_final,
+                                 void* stream);
+
 /* mss_propagate that also writes the expected spin projection of every
  * state as the states are formed (the projection of mss_spin_projection,
  * fused into the last pass of the product, so the states are not read

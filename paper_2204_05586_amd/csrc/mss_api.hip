@@ -334,6 +334,14 @@ mss_status propagate(int32_t spin_twice, int64_t n_samples, const double* U, con
 }
 }  // namespace
 
+namespace mss {
+mss_status api_propagate(int32_t spin_twice, int64_t n_samples, const double* U,
+                         const double* psi0, double* psi, double* psi_final, void* ws,
+                         size_t ws_bytes, void* stream) {
+  return propagate(spin_twice, n_samples, U, psi0, psi, psi_final, nullptr, ws, ws_bytes, stream);
+}
+}  // namespace mss
+
 extern "C" {
 
 const char* mss_status_str(mss_status s) {

@@ -35,7 +35,7 @@ EXPORTS = [
     "mss_adjoint_plan_destroy", "mss_sampler_create", "mss_sampler_log", "mss_sampler_integrate",
     "mss_sampler_solve", "mss_sampler_destroy", "mss_batch_plan_create_sampled",
     "mss_sampler_create_for_terms", "mss_sampler_min_params", "mss_propagate_spin",
-    "mss_adjoint_plan_create_compiled", "mss_solve_batch",
+    "mss_adjoint_plan_create_compiled", "mss_propagate_noalloc", "mss_solve_batch",
     "mss_adjoint_population",
 ]
 
@@ -139,6 +139,7 @@ def lib() -> C.CDLL:
         L.mss_integrate.argtypes = [PP, vp, vp, vp, C.POINTER(Launch), vp]
         L.mss_propagate.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, vp, vp, sz, vp]
         L.mss_propagate_spin.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_propagate_noalloc.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, vp, vp]
         L.mss_solve.argtypes = [PP, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.mss_spin_projection.argtypes = [C.c_int32, C.c_int64, vp, vp, vp]
         L.mss_spin_projection.restype = C.c_int
@@ -201,7 +202,7 @@ def lib() -> C.CDLL:
                      "mss_sampler_integrate", "mss_sampler_solve",
                      "mss_batch_plan_create_sampled", "mss_sampler_create_for_terms",
                      "mss_propagate_spin", "mss_server_request_slices",
-                     "mss_adjoint_plan_create_compiled",
+                     "mss_adjoint_plan_create_compiled", "mss_propagate_noalloc",
                      "mss_solve_batch", "mss_adjoint_population"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -338,6 +339,16 @@ def propagate(spin_twice: int, U, psi0, psi, psi_final=None, ws=None, stream=Non
         check(lib().mss_propagate_spin(int(spin_twice), K, _ptr(U), _ptr(psi0), _ptr(psi),
                                        _ptr(psi_final), _ptr(spin), _ptr(ws), nbytes,
                                        _stream(stream)))
+
+
+def propagate_noalloc(spin_twice: int, U, psi0, psi, psi_final=None, stream=None,
+                      n_samples=None) -> None:
+    """mss_propagate_noalloc: mss_propagate with the library's static scan
+    scratch instead of a workspace (no allocation; calls overlapping on one
+    GPU race).  n_samples defaults to U's length."""
+    K = int(U.shape[0]) if n_samples is None else int(n_samples)
+    check(lib().mss_propagate_noalloc(int(spin_twice), K, _ptr(U), _ptr(psi0), _ptr(psi),
+                                      _ptr(psi_final), _stream(stream)))
 
 
 def solve_into(prob, params, psi0, psi, psi_final=None, U=None, time=None, ws=None,

@@ -156,6 +156,21 @@ def test_propagate_spin_requires_output():
     assert st == native.MSS_E_INVALID and "spin_twice" in native.last_error()
 
 
+def test_propagate_noalloc_checks_before_any_device_call():
+    """Bad arguments and sizes beyond the static scratch are refused on the
+    host (this container has no GPU, so any device call would fail)."""
+    L = native.lib()
+    buf = (C.c_double * 64)()
+    for spin_twice, kmax in ((2, 11_141_120), (1, 22_280_192)):
+        st = L.mss_propagate_noalloc(spin_twice, kmax + 1, buf, buf, buf, None, None)
+        assert st == native.MSS_E_INVALID and "scan scratch" in native.last_error()
+        assert native.propagate_workspace_size(spin_twice, kmax) <= 8 << 20
+    st = L.mss_propagate_noalloc(3, 4, buf, buf, buf, None, None)
+    assert st == native.MSS_E_INVALID and "spin_twice" in native.last_error()
+    st = L.mss_propagate_noalloc(2, 0, buf, buf, buf, None, None)
+    assert st == native.MSS_E_INVALID and "n_samples" in native.last_error()
+
+
 def test_one_shot_calls_check_before_any_device_call():
     L = native.lib()
     buf = (C.c_double * 64)()
