@@ -114,8 +114,6 @@ struct ScanLevels {
   int64_t n[8];         // n[0] = K, n[l] = elements at level l
   size_t agg_off[8];    // workspace offsets of level-l aggregates (l >= 1)
   size_t state_off[8];  // workspace offsets of level-l entering states (l >= 1)
-  bool one_pass;        // shape of the one-launch scan: 1 or 2 levels, <= 16 level-1 tiles
-  size_t sync_off;      // its call counter and level-0 tile tags (when one_pass)
   size_t bytes;
 };
 
@@ -128,12 +126,7 @@ ScanLevels plan_scan(int N, int64_t K) {
     ++l;
   }
   s.n_levels = l;
-  s.one_pass = l == 1 || (l == 2 && (s.n[1] + kScanTile - 1) / kScanTile <= 16);
   size_t off = 0;
-  if (s.one_pass) {
-    s.sync_off = 0;
-    off = kScanSyncBytes + align256((size_t)s.n[1] * sizeof(unsigned long long));
-  }
   for (int j = 1; j <= l; ++j) {
     s.agg_off[j] = off;
     off += align256((size_t)s.n[j] * 2 * N * N * sizeof(double));
@@ -300,13 +293,6 @@ mss_status propagate(int32_t spin_twice, int64_t n_samples, const double* U, con
   M[0] = U;
   for (int l = 1; l <= lv.n_levels; ++l) M[l] = (const double*)(w + lv.agg_off[l]);
   hipError_t e;
-  if (lv.one_pass && scan_one_pass_fits(N, lv.n[1])) {
-    e = launch_scan_one_pass(N, U, lv.n[0], (double*)M[1], (double*)(w + lv.state_off[1]),
-                             lv.n[1], lv.n_levels, psi0, psi, psi_final, spin, w + lv.sync_off,
-                             st);
-    if (e != hipSuccess) return api_hip_fail(e, "scan launch");
-    return api_ok();
-  }
   if (lv.n_levels == 2 && (lv.n[1] + kScanTile - 1) / kScanTile <= 16) {
     // level 0 up, levels 1-2 in one workgroup, level 0 down
     e = launch_scan_reduce(N, M[0], lv.n[0], (double*)M[1], st);

@@ -1,11 +1,9 @@
-"""The single-sequence scan in one launch (mss_propagate with one or two
-levels above the operators): bitwise the result of the batch plan's
-level-by-level scan on the same operators, within rounding of the oracle's
-sequential product, correct on repeated calls through one workspace and in
-replays of a captured graph, and its bounded waits never run out.  Shapes
-cover both sides of every switch: one level (K <= 65536), two levels,
-the largest grid it takes for spin-1 (262144) and the first it leaves to
-separate launches, and three levels."""
+"""The single-sequence scan (mss_propagate) across its shapes: bitwise the
+result of the batch plan's segmented scan on the same operators, within
+rounding of the oracle's sequential product, and bitwise repeatable through
+one workspace and in replays of a captured graph.  Shapes cover one level
+above the operators (K <= 65536), two levels with the upper two in one
+workgroup (at most 16 level-1 tiles) and beyond it, and three levels."""
 import numpy as np
 import pytest
 
@@ -41,43 +39,19 @@ def _unitaries(torch, N, K, seed):
     return (D[:, :, None] * Vd[None]).contiguous()
 
 
-M64 = (1 << 64) - 1
-
-
-def call_tag(c):
-    """The SplitMix64 finalizer the kernel tags a call with."""
-    c &= M64
-    c ^= c >> 30
-    c = (c * 0xBF58476D1CE4E5B9) & M64
-    c ^= c >> 27
-    c = (c * 0x94D049BB133111EB) & M64
-    c ^= c >> 31
-    return c
-
-
-def _header(ws):
-    """(epoch, whether the call numbered epoch ran out of a wait) of a
-    one-launch scan workspace."""
-    import torch
-    h = ws[:256].view(dtype=torch.int64).cpu().numpy().astype(np.uint64)
-    epoch = int(h[0])
-    return epoch, int(h[2]) == call_tag(epoch)
-
-
 @pytest.mark.parametrize("N,K", SHAPES, ids=[f"N{n}-K{k}" for n, k in SHAPES])
-def test_one_pass_equals_level_scan_and_oracle(dev, oracle, N, K):
+def test_scan_equals_batch_scan_and_oracle(dev, oracle, N, K):
     torch = dev
     from paper_2204_05586_amd import native
-    print(f"[gpu] one-pass scan N={N} K={K}", flush=True)
+    print(f"[gpu] scan N={N} K={K}", flush=True)
     U = _unitaries(torch, N, K, seed=7 * K + N)
     rng = np.random.default_rng(K + N)
     psi0 = W.random_state(N, rng)
     ws = native.alloc_workspace(native.propagate_workspace_size(N - 1, K))
-    # the workspace starts out holding operator bits (near-identical doubles)
+    # the workspace starts out holding operator bits
     junk = U.view(-1).view(torch.uint8)
     n = min(ws.numel(), junk.numel())
     ws[:n].copy_(junk[:n])
-    e_before = int(ws[:8].view(torch.int64).item()) & M64
     psi = torch.empty((K, N), dtype=torch.complex128, device="cuda")
     fin = torch.empty((N,), dtype=torch.complex128, device="cuda")
     native.propagate(N - 1, U, native.device_state(psi0), psi, fin, ws)
@@ -95,19 +69,13 @@ def test_one_pass_equals_level_scan_and_oracle(dev, oracle, N, K):
     d = max(np.max(np.abs(psi.cpu().numpy() - ref_psi)), np.max(np.abs(fin.cpu().numpy() - ref_fin)))
     print(f"N={N} K={K}: max |d| vs the oracle's sequential product {d:.2e}", flush=True)
     assert d < 1e-11
-    epoch, failed = _header(ws)
-    one_pass = epoch == (e_before + 1) & M64
-    print(f"N={N} K={K}: one launch {one_pass}", flush=True)
-    if 256 < K <= 262_144:
-        assert one_pass and not failed
 
 
 @pytest.mark.parametrize("N,K", [(2, 10_000), (3, 200_000)])
-def test_one_pass_repeated_calls_and_graph_replays(dev, N, K):
-    """Calls through one workspace each see their own call number: eager
-    calls, then a captured graph replayed three times with eager work in
-    between, all bitwise equal; the workspace's call counter advances by one
-    per call or replay and no wait runs out."""
+def test_scan_repeated_calls_and_graph_replays(dev, N, K):
+    """Calls through one workspace, then a captured graph replayed three
+    times with eager work (other operators through the same workspace) in
+    between: all bitwise equal."""
     torch = dev
     from paper_2204_05586_amd import native
     U = _unitaries(torch, N, K, seed=N * 31 + K)
@@ -116,16 +84,10 @@ def test_one_pass_repeated_calls_and_graph_replays(dev, N, K):
     ws = native.alloc_workspace(native.propagate_workspace_size(N - 1, K))
     ref = torch.empty((K, N), dtype=torch.complex128, device="cuda")
     other = torch.empty_like(ref)
-    print(f"[gpu] one-pass repeated N={N} K={K}", flush=True)
+    print(f"[gpu] scan repeated N={N} K={K}", flush=True)
     native.propagate(N - 1, U, psi0, ref, None, ws)
-    torch.cuda.synchronize()
-    e0, failed = _header(ws)
-    assert not failed
     for i in range(3):
         native.propagate(N - 1, U2 if i % 2 else U, psi0, other, None, ws)
-    torch.cuda.synchronize()
-    e1, failed = _header(ws)
-    assert e1 == e0 + 3 and not failed
     native.propagate(N - 1, U, psi0, other, None, ws)
     torch.cuda.synchronize()
     assert torch.equal(other, ref)
@@ -133,11 +95,10 @@ def test_one_pass_repeated_calls_and_graph_replays(dev, N, K):
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
-    print(f"[gpu] one-pass graph capture N={N} K={K}", flush=True)
+    print(f"[gpu] scan graph capture N={N} K={K}", flush=True)
     with torch.cuda.graph(g, stream=s):
         native.propagate(N - 1, U, psi0, out, None, ws)
     torch.cuda.synchronize()
-    e2, _ = _header(ws)
     for r in range(3):
         out.zero_()
         g.replay()
@@ -145,5 +106,3 @@ def test_one_pass_repeated_calls_and_graph_replays(dev, N, K):
         assert torch.equal(out, ref), r
         native.propagate(N - 1, U2, psi0, other, None, ws)  # eager work between replays
         torch.cuda.synchronize()
-    e3, failed = _header(ws)
-    assert e3 == e2 + 6 and not failed

@@ -71,10 +71,7 @@ def test_validation_rejects_bad_problems():
 
 
 def test_workspace_sizes():
-    """Per level above the operators: aggregates and entering states; a scan
-    the one-launch kernel can take (one level, or two with at most 16
-    level-1 tiles) adds its 256-byte call counter and a tag per level-0
-    tile."""
+    """Per level above the operators: aggregates and entering states."""
     tile = 256
     for spin_twice, K in [(1, 1), (1, 256), (2, 257), (2, 200_000), (2, 65_537), (1, 1 << 20),
                           (1, (1 << 20) + 1)]:
@@ -86,8 +83,6 @@ def test_workspace_sizes():
             n = -(-n // tile)
             sizes.append(n)
             expect += -(-(n * 2 * N * N * 8) // 256) * 256 + -(-(n * 2 * N * 8) // 256) * 256
-        if len(sizes) == 1 or (len(sizes) == 2 and sizes[1] <= 16):
-            expect += 256 + -(-(sizes[0] * 8) // 256) * 256
         assert native.propagate_workspace_size(spin_twice, K) == expect
         prob = W.random_problem(np.random.default_rng(0), spin_twice, K, 3)
         assert native.workspace_size(prob, True) == expect

@@ -1,8 +1,8 @@
 """mss_propagate_noalloc (the ordered product with the library's static
 scan scratch, no allocation) against mss_propagate with an allocated
 workspace: calls in a row through the same scratch, each smaller than the
-one before, across the one-launch and level-by-level scan shapes and both
-spins, plus the size limit."""
+one before, across the scan's shapes and both
+spins, plus the size limit.""" 
 import numpy as np
 import pytest
 
@@ -33,8 +33,8 @@ def _operators(spin_twice, K, seed):
 def test_noalloc_matches_propagate(torch_dev):
     import torch
     from paper_2204_05586_amd import native
-    # 5e6 spin-1: three levels, level by level; 300,001: the one-launch scan;
-    # then spin-1/2 one-launch, one level, and a single tile (no scratch)
+    # 5e6 spin-1: three levels; 300,001: two levels, the upper two in one
+    # workgroup; then spin-1/2 with one level, and single tiles (no scratch)
     cases = [(2, 5_000_001), (2, 300_001), (1, 70_001), (1, 1000), (2, 200)]
     for i, (spin_twice, K) in enumerate(cases):
         print(f"[gpu] noalloc case spin_twice={spin_twice} K={K}", flush=True)
