@@ -81,6 +81,25 @@ __device__ __forceinline__ int64_t wave_broadcast(int64_t v) {
   return ((int64_t)hi << 32) | (uint32_t)lo;
 }
 
+// Largest i in [0, n) with key(i) <= x, for a non-decreasing key with
+// key(0) <= x, found by the whole wave: each step splits what is left into
+// 64 buckets, lane l tests the first key of bucket l, and the highest lane
+// whose key is <= x picks the bucket.  Two dependent vector loads for 4096
+// keys instead of twelve dependent scalar loads of a binary search.
+template <class Key>
+__device__ __forceinline__ int wave_search(const Key& key, int n, int64_t x, int lane) {
+  int base = 0, span = n;
+  while (span > 1) {
+    const int stride = (span + 63) >> 6;
+    const bool ok = lane * stride < span && key(base + lane * stride) <= x;
+    const unsigned long long m = __ballot(ok);
+    const int last = 63 - __builtin_clzll(m);  // m != 0: key(base) <= x
+    base += last * stride;
+    span = min(stride, span - last * stride);
+  }
+  return base;
+}
+
 // One work item: 64 / S consecutive intervals of descriptor s, S lane-slices
 // each.  source(A, s) gives the field source of the descriptor.
 template <int N, class Source>
@@ -135,19 +154,18 @@ __device__ __forceinline__ bool wave_uniform(bool b) {
 }
 
 // The state the unit with tag `tag` left in the slot (every lane receives
-// it): lanes 0 .. 4N - 1 poll one word each until all carry the tag.  The
-// loop's exits are wave-uniform.  false when the bound ran out, or a wait
+// it): lanes 0 .. 4N - 1 hold one word each, v (read earlier), and read it
+// again until all carry the tag.  The loop's exits are wave-uniform.  false when the bound ran out, or a wait
 // of this run already had (then the kernel only drains its queue; the
 // states are undefined).
 template <int N>
 __device__ __forceinline__ bool chain_receive(ChainSlot* slot, unsigned tag, ChainSync* sync,
-                                              int lane, double* xr, double* xi) {
+                                              int lane, unsigned long long v, double* xr,
+                                              double* xi) {
   const bool mine = lane < 4 * N;
-  unsigned long long v = 0ull;
   bool ok = true;
   const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
   for (;;) {
-    if (mine) v = chain_read(&slot->w[lane]);
     if (wave_uniform(__all(!mine || (unsigned)(v >> 32) == tag))) break;
     // not there yet: give up at once if a wait of this run already ran out
     unsigned long long f = 0ull;
@@ -164,6 +182,7 @@ __device__ __forceinline__ bool chain_receive(ChainSlot* slot, unsigned tag, Cha
       break;
     }
     __builtin_amdgcn_s_sleep(2);
+    if (mine) v = chain_read(&slot->w[lane]);
   }
   const unsigned lo32 = (unsigned)v;
 #pragma unroll
@@ -215,6 +234,12 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
   const int64_t k = kb + jl;
   const bool active = k < s.K_total;
   using Terms = decltype(source(A, s));
+  // the state the unit before left is read now: with a round's units spread
+  // over the queue it is usually there already, and the read's round trip
+  // then overlaps this unit's integration
+  const bool first = wave_uniform(unit == 0);
+  unsigned long long early = 0ull;
+  if (!first && lane < 4 * N) early = chain_read(&slot->w[lane]);
   Mat<N> P;
   double tk;
   bool done = false;
@@ -242,14 +267,14 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
   }
   // the entering state: psi0, or what the unit before left
   double xr[N], xi[N];
-  if (wave_uniform(unit == 0)) {
+  if (first) {
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       xr[a] = s.psi0[2 * a];
       xi[a] = s.psi0[2 * a + 1];
     }
   } else {
-    (void)chain_receive<N>(slot, (unsigned)unit, A.sync, lane, xr, xi);
+    (void)chain_receive<N>(slot, (unsigned)unit, A.sync, lane, early, xr, xi);
   }
   // y = P_j x: the state leaving interval j; the one entering it is the
   // previous interval's leaving state (x for the first)
@@ -316,7 +341,10 @@ template <class Source>
 __device__ __forceinline__ void chained_integrate_loop(const IntegrateWorkArgs& A,
                                                        const Source& source) {
   const int lane = threadIdx.x & 63;
-  for (;;) {
+  int64_t item = 0;
+  if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
+  item = wave_broadcast(item);
+  while (item < A.n_items) {
     // every lane must be here: a wave without lane 0 would take no unit from
     // the counter and broadcast another lane's 0 instead; it stops and
     // marks the run failed (never seen with the loop compiled uniform)
@@ -326,16 +354,15 @@ __device__ __forceinline__ void chained_integrate_loop(const IntegrateWorkArgs& 
                                     __HIP_MEMORY_SCOPE_AGENT);
       break;
     }
-    int64_t item = 0;
-    if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
-    item = wave_broadcast(item);
-    if (item >= A.n_items) break;
-    int lo = 0, hi = A.n_groups - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (A.group_item0[mid] <= item) lo = mid;
-      else hi = mid - 1;
-    }
+    // while a whole grid's worth of units remains, the next unit is taken
+    // now, so the counter's round trip overlaps this unit's work (a held unit
+    // is younger than the one its wave works on, so the oldest unfinished
+    // unit always runs and every wait still ends); near the end it is taken
+    // afterwards, so that the last units go to idle waves
+    const bool ahead = item + (int64_t)gridDim.x * (blockDim.x >> 6) < A.n_items;
+    int64_t next = 0;
+    if (ahead && lane == 0) next = (int64_t)atomicAdd(A.counter, 1ull);
+    const int lo = wave_search([&](int i) { return A.group_item0[i]; }, A.n_groups, item, lane);
     // the unit's round and simulation, made explicitly wave-uniform so that
     // every branch on the descriptor is a scalar branch
     const int64_t off = item - A.group_item0[lo];
@@ -345,31 +372,35 @@ __device__ __forceinline__ void chained_integrate_loop(const IntegrateWorkArgs& 
     const SimDesc& s = A.sims[sim];
     if (s.spin_twice == 2) chained_unit<3>(A, s, A.slots + sim, round, lane, source);
     else chained_unit<2>(A, s, A.slots + sim, round, lane, source);
+    if (!ahead && lane == 0) next = (int64_t)atomicAdd(A.counter, 1ull);
+    item = wave_broadcast(next);
   }
 }
 
 // Persistent loop: each wave takes items from the counter until it passes
 // the item count, so every wave exits once the queue is drained and no wave
-// waits for another.
+// waits for another.  While a whole grid's worth of items remains, the next
+// item is taken before the current one is worked on, so the counter's round
+// trip overlaps that work; near the end it is taken afterwards, so that the
+// last items go to idle waves.
 template <class Source>
 __device__ __forceinline__ void work_integrate_loop(const IntegrateWorkArgs& A,
                                                     const Source& source) {
   const int lane = threadIdx.x & 63;
-  for (;;) {
-    int64_t item = 0;
-    if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
-    item = wave_broadcast(item);
-    if (item >= A.n_items) break;
-    int lo = 0, hi = A.n_sims - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (A.sims[mid].item_off <= item) lo = mid;
-      else hi = mid - 1;
-    }
+  int64_t item = 0;
+  if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
+  item = wave_broadcast(item);
+  while (item < A.n_items) {
+    const bool ahead = item + (int64_t)gridDim.x * (blockDim.x >> 6) < A.n_items;
+    int64_t next = 0;
+    if (ahead && lane == 0) next = (int64_t)atomicAdd(A.counter, 1ull);
+    const int lo = wave_search([&](int i) { return A.sims[i].item_off; }, A.n_sims, item, lane);
     const SimDesc& s = A.sims[lo];
     const int64_t local = item - s.item_off;
     if (s.spin_twice == 2) work_item<3>(A, s, local, lane, source);
     else work_item<2>(A, s, local, lane, source);
+    if (!ahead && lane == 0) next = (int64_t)atomicAdd(A.counter, 1ull);
+    item = wave_broadcast(next);
   }
 }
 
