@@ -796,12 +796,36 @@ __device__ __forceinline__ void exp_full(const double th[kFullComps], int tau, M
   E.r[2][2] += 1.0;
 }
 
+// The wave's issue priority, rotated with the fine step: the hardware slot
+// number offsets the rotation, so waves sharing a SIMD take turns at the
+// highest of the four levels and advance at the same rate.  (Among waves
+// of equal priority the arbiter prefers the older one, which in a
+// persistent launch with two blocks per CU runs the first block's waves
+// about 2.4 times as fast as the second's for the whole launch.)  Lanes
+// may disagree on the step (several slices per interval): the first active
+// lane's sets the level.
+__device__ __forceinline__ void rotate_priority(int step, int slot) {
+  switch (__builtin_amdgcn_readfirstlane(step + slot) & 3) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+  }
+}
+
+// The wave's slot on its SIMD (HW_ID bits 3:0).
+__device__ __forceinline__ int wave_slot() {
+  return (int)(__builtin_amdgcn_s_getreg(4 | (3 << 11)) & 15u);
+}
+
 // Operator of one interval (rows a1-a9) computed by S = 2^sl cooperating
 // lanes: slice s integrates fine steps [s L / S, (s + 1) L / S) and the
 // partial products are combined in order with wave shuffles; the full
 // U_k (frame exit applied) ends up in the lane with s == 0.  Every lane of
-// the wave must call this (the shuffles need the whole wave).
-template <int N, bool FULL = false, class Terms>
+// the wave must call this (the shuffles need the whole wave).  SHARE: the
+// wave rotates its issue priority every fine step (rotate_priority), for
+// launches whose waves wait on one another's results.
+template <int N, bool FULL = false, bool SHARE = false, class Terms>
 __device__ __forceinline__ void interval_operator(const Terms& terms, const double* __restrict__ params,
                                                   double t_start, double Dt, double dt, int L,
                                                   int tau, int frame, int method, int64_t k, int s,
@@ -813,11 +837,13 @@ __device__ __forceinline__ void interval_operator(const Terms& terms, const doub
     interval_setup(terms, params, t_start, Dt, k, frame, &tk, &wr);
     const int l0 = (int)(((int64_t)s * L) >> sl);
     const int l1 = (int)(((int64_t)(s + 1) * L) >> sl);
+    const int slot = SHARE ? wave_slot() : 0;
     if constexpr (FULL) {
       if (method == 0) {
         NodeRotations rot;
         if (wr != 0.0) rot.start(wr, l0, dt);
         for (int l = l0; l < l1; ++l) {
+          if constexpr (SHARE) rotate_priority(l, slot);
           double th1[kFullComps], th2[kFullComps];
           cf4_angles_full(terms, params, tk, l, dt, wr, rot, th1, th2);
           if (wr != 0.0) rot.advance();
@@ -829,6 +855,7 @@ __device__ __forceinline__ void interval_operator(const Terms& terms, const doub
         }
       } else {
         for (int l = l0; l < l1; ++l) {
+          if constexpr (SHARE) rotate_priority(l, slot);
           double th[kFullComps];
           euler_angles_full(terms, params, tk, l, dt, wr, method, th);
           Mat<3> E;
@@ -840,6 +867,7 @@ __device__ __forceinline__ void interval_operator(const Terms& terms, const doub
       NodeRotations rot;
       if (wr != 0.0) rot.start(wr, l0, dt);
       for (int l = l0; l < l1; ++l) {
+        if constexpr (SHARE) rotate_priority(l, slot);
         double th1[4], th2[4];
         cf4_angles(terms, params, tk, l, dt, wr, rot, th1, th2);
         if (wr != 0.0) rot.advance();
@@ -851,6 +879,7 @@ __device__ __forceinline__ void interval_operator(const Terms& terms, const doub
       }
     } else {
       for (int l = l0; l < l1; ++l) {
+        if constexpr (SHARE) rotate_priority(l, slot);
         double th[4];
         euler_angles(terms, params, tk, l, dt, wr, method, th);
         Mat<N> E;

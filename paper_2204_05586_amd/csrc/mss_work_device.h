@@ -245,14 +245,16 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
   bool done = false;
   if constexpr (N == 3 && has_full_basis<Terms>::value) {
     if (s.full) {
-      interval_operator<3, true>(source(A, s), s.params, s.t_start, s.dt_out, s.dt, s.n_fine,
-                                 s.tau, s.frame, s.method, k, slice, sl, active, P, &tk);
+      interval_operator<3, true, true>(source(A, s), s.params, s.t_start, s.dt_out, s.dt,
+                                       s.n_fine, s.tau, s.frame, s.method, k, slice, sl, active,
+                                       P, &tk);
       done = true;
     }
   }
   if (!done)
-    interval_operator<N>(source(A, s), s.params, s.t_start, s.dt_out, s.dt, s.n_fine, s.tau,
-                         s.frame, s.method, k, slice, sl, active, P, &tk);
+    interval_operator<N, false, true>(source(A, s), s.params, s.t_start, s.dt_out, s.dt,
+                                      s.n_fine, s.tau, s.frame, s.method, k, slice, sl, active,
+                                      P, &tk);
   if (active && slice == 0 && s.U) store_mat<N>(s.U + (size_t)k * 2 * N * N, P);
   if (!active) set_identity<N>(P);
   // P_j = U_j ... U_0 over the unit's intervals (lanes with slice 0; the
