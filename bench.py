@@ -37,23 +37,28 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 
-# HBM traffic of the integrator per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# passes, calibrated against a 1 GiB copy (FETCH x 2.000, WRITE x 1.000), keyed by
-# the hash of the kernel sources it was taken with: reported only while the
-# sources are unchanged.
+# HBM traffic per launch of the batched integrators from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes, calibrated against a 1 GiB copy (FETCH x 2.000, WRITE x 1.000),
+# keyed by the hash of the kernel sources they were taken with: reported only while
+# the sources are unchanged.
 MEASURED_TRAFFIC = {
+    ("mss_user_work_chained", "batched_sensing"): {
+        "src": "d1cab8ae5482b759",
+        "fetch_kib": 496467.3, "write_kib": 25013906.3,
+        "bytes": int(round((496467.3 * 2.000 + 25013906.3 * 1.000) * 1024)),
+    },
     ("mss_user_work_integrate", "batched_sensing"): {
-        "src": "d894a1a6ee8ec244",
-        "fetch_kib": 4520.8125, "write_kib": 64034971.0,
-        "bytes": int(round((4520.8125 * 2.000 + 64034971.0 * 1.000) * 1024)),
+        "src": "d1cab8ae5482b759",
+        "fetch_kib": 3781.1, "write_kib": 64036183.8,
+        "bytes": int(round((3781.1 * 2.000 + 64036183.8 * 1.000) * 1024)),
     },
 }
 
 
-# sources that define the batched integrator: the field program compiled into
-# the persistent work-queue kernel at run time (mss_user_work_integrate: the
-# generated field function, the device headers it is compiled with, the
-# compile options and the launch)
+# sources that define the batched integrators: the field program compiled into
+# the persistent work-queue kernels at run time (mss_user_work_chained and
+# mss_user_work_integrate: the generated field function, the device headers they
+# are compiled with, the compile options and the launch)
 INTEGRATOR_SOURCES = ("mss_device.h", "mss_internal.h", "mss_work.h", "mss_work_device.h",
                       "mss_work.hip", "mss_user_kernels.h", "mss_sampler.hip")
 
@@ -211,7 +216,8 @@ def bench_batched(problems, steps: int, warmup: int, tune: bool, specialise: boo
     field program compiled into the persistent integrator, which also forms
     the states; no operator buffer), replayed `steps` times after at least
     3 warm-up replays, each replay between HIP events on the stream it runs
-    on.  Then the separate-scan plan (operators kept in the workspace, then
+    on (with more replays after the timed ones when `steps` < 10, so that
+    the replay statistics cover at least 10).  Then the separate-scan plan (operators kept in the workspace, then
     the segmented scan) eagerly, integrator and scan timed apart, and the
     interpreter's integrator on its buffers."""
     import torch
@@ -236,7 +242,16 @@ def bench_batched(problems, steps: int, warmup: int, tune: bool, specialise: boo
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    replay = [a.elapsed_time(b) for a, b in evs]
+    # the replay statistics cover at least 10 replays: when fewer steps are
+    # timed, the rest run after the timed region
+    extra = [[torch.cuda.Event(enable_timing=True) for _ in range(2)]
+             for _ in range(max(0, 10 - steps))]
+    for a, b in extra:
+        a.record(stream)
+        plan.run(bufs, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    replay = [a.elapsed_time(b) for a, b in evs + extra]
     info = plan.info()
     specialized = plan.specialized
     ws_bytes = int(bufs["ws"].numel())
@@ -578,7 +593,7 @@ def accuracy_study(ref_fine: int = 500, reps: int = 3) -> dict:
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batched_sensing",
                     choices=["batched_sensing", "spin_one_sensing", "spin_half_rabi"])
