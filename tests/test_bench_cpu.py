@@ -34,7 +34,8 @@ def test_flops_per_fine_step():
 
 def test_traffic_table_names_kernels_the_bench_reports():
     for (kernel, workload), v in bench.MEASURED_TRAFFIC.items():
-        assert kernel in ("mss_user_work_integrate", "work_integrate_kernel")
+        assert kernel in ("mss_user_work_chained", "mss_user_work_integrate",
+                          "work_integrate_kernel")
         assert workload == "batched_sensing"
         assert v["bytes"] == int(round((v["fetch_kib"] * 2.0 + v["write_kib"]) * 1024))
         assert len(v["src"]) == 16
