@@ -293,7 +293,7 @@ mss_status propagate(int32_t spin_twice, int64_t n_samples, const double* U, con
   M[0] = U;
   for (int l = 1; l <= lv.n_levels; ++l) M[l] = (const double*)(w + lv.agg_off[l]);
   hipError_t e;
-  if (lv.n_levels == 2 && (lv.n[1] + kScanTile - 1) / kScanTile <= 16) {
+  if (lv.n_levels == 2 && (lv.n[1] + kScanTile - 1) / kScanTile <= kTopWaves) {
     // level 0 up, levels 1-2 in one workgroup, level 0 down
     e = launch_scan_reduce(N, M[0], lv.n[0], (double*)M[1], st);
     if (e == hipSuccess)

@@ -40,30 +40,67 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const double* __restric
                 after_last, spin);
 }
 
-// Levels 1 and 2 of a two-level scan in one workgroup (n1 <= 16 tiles):
-// wave w reduces level-1 tile w into LDS, wave 0 scans those aggregates
-// from start, then wave w applies its tile from the state entering it.  The
-// same tile routines on the same data as the separate launches, so the
-// result is bitwise the same; the LDS holds the level-2 aggregates and
-// entering states between the phases.
-constexpr int kTopWaves = 16;
+// Levels 1 and 2 of a two-level scan in one workgroup (n1 <= kTopWaves tiles of
+// kScanTile level-1 elements), with one scan pass per wave: wave w forms
+// the inclusive products P_j of its tile (lane_scan, as tile_reduce and
+// tile_apply do) and leaves the tile total in LDS; wave 0 applies the
+// level-2 tile of totals from start (tile_apply); every wave then applies
+// its own tile from the state entering it with the P_j it still holds.
+// The arithmetic is that of the separate reduce and apply launches, so the
+// states are bitwise the same.
 
 template <int N>
 __global__ void __launch_bounds__(64 * kTopWaves) scan_top_kernel(const double* __restrict__ M1,
                                                                   int64_t n1,
                                                                   const double* __restrict__ start,
                                                                   double* __restrict__ before1) {
-  __shared__ double agg2[kTopWaves * 2 * N * N];
-  __shared__ double before2[kTopWaves * 2 * N];
+  constexpr int E = kScanPerLane;
+  __shared__ double total[kTopWaves * 2 * N * N];
+  __shared__ double enter[kTopWaves * 2 * N];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t n2 = (n1 + kScanTile - 1) / kScanTile;
-  tile_reduce<N, kScanPerLane>(M1, n1, wave, lane, agg2 + (size_t)wave * 2 * N * N);
+  const int64_t n2 = blockDim.x >> 6;
+  const int64_t base = (int64_t)wave * kScanTile + (int64_t)lane * E;
+  Mat<N> P;
+  lane_scan<N, E>(M1, n1, base, lane, P);
+  if (lane == 63) store_mat<N>(total + (size_t)wave * 2 * N * N, P);
   __syncthreads();
-  if (wave == 0) tile_apply<N, kScanPerLane>(agg2, n2, 0, lane, true, start, before2, nullptr);
+  if (wave == 0) tile_apply<N, E>(total, n2, 0, lane, true, start, enter, nullptr);
   __syncthreads();
-  tile_apply<N, kScanPerLane>(M1, n1, wave, lane, true, before2 + (size_t)wave * 2 * N, before1,
-                              nullptr);
+  // the state entering this lane's first element: P_{lane-1} x (I x for lane 0)
+  double xr[N], xi[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    xr[a] = enter[wave * 2 * N + 2 * a];
+    xi[a] = enter[wave * 2 * N + 2 * a + 1];
+  }
+  Mat<N> X = shfl_up_mat<N>(P, 1);
+  if (lane == 0) set_identity<N>(X);
+  double vr[N], vi[N];
+  matvec<N>(X, xr, xi, vr, vi);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int64_t idx = base + e;
+    if (idx < n1) {
+      double* o = before1 + (size_t)idx * 2 * N;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        o[2 * a] = vr[a];
+        o[2 * a + 1] = vi[a];
+      }
+      if (e + 1 < E) {
+        Mat<N> Y;
+        load_mat<N>(M1 + (size_t)idx * 2 * N * N, Y);
+        double wr_[N], wi_[N];
+        matvec<N>(Y, vr, vi, wr_, wi_);
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          vr[a] = wr_[a];
+          vi[a] = wi_[a];
+        }
+      }
+    }
+  }
 }
 
 // <J_a> = psi^H J_a psi for one state per lane (a = x, y, z), written as

@@ -33,6 +33,25 @@ __device__ __forceinline__ void project_spin(const double* vr, const double* vi,
   j3[2] = jz;
 }
 
+// y = M x for a complex N x N matrix and an N-vector (re / im parts apart).
+template <int N>
+__device__ __forceinline__ void matvec(const Mat<N>& M, const double* xr, const double* xi,
+                                       double* yr, double* yi) {
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      re = fma(M.r[a][b], xr[b], re);
+      re = fma(-M.i[a][b], xi[b], re);
+      im = fma(M.r[a][b], xi[b], im);
+      im = fma(M.i[a][b], xr[b], im);
+    }
+    yr[a] = re;
+    yi[a] = im;
+  }
+}
+
 // Product of the lane's (up to) E consecutive matrices, later on the left
 // (the identity for a lane past the end).  The first matrix is loaded as
 // the start value: multiplying it into the identity would give the same
@@ -53,19 +72,34 @@ __device__ __forceinline__ void lane_product(const double* __restrict__ M, int64
   }
 }
 
+// Inclusive products over a tile: lane j ends with P_j = Q_j ... Q_0, Q_j
+// the product of its E elements (a six-level shuffle scan).  Every lane
+// must call this.
+template <int N, int E>
+__device__ __forceinline__ void lane_scan(const double* __restrict__ M, int64_t n, int64_t base,
+                                          int lane, Mat<N>& P) {
+  lane_product<N, E>(M, n, base, P);
+  for (int d = 1; d < 64; d <<= 1) {
+    const Mat<N> o = shfl_up_mat<N>(P, d);
+    if (lane >= d) {
+      Mat<N> t;
+      matmul<N>(P, o, t);
+      P = t;
+    }
+  }
+}
+
 // Tile reduce: agg = M[tT + T - 1] ... M[tT] of tile t (T = 64 E), one
-// wave per tile.  M points at element 0 of the sequence, n its length.
+// wave per tile: the last lane's inclusive product, so that a tile's
+// aggregate is bit for bit the total that tile_apply's scan forms.  M
+// points at element 0 of the sequence, n its length.
 template <int N, int E>
 __device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_t n, int64_t tile,
                                             int lane, double* __restrict__ agg_out) {
   const int64_t base = tile * (64 * E) + (int64_t)lane * E;
-  Mat<N> Q;
-  lane_product<N, E>(M, n, base, Q);
-  for (int d = 1; d < 64; d <<= 1) {
-    const Mat<N> o = shfl_down_mat<N>(Q, d);
-    if ((lane & (2 * d - 1)) == 0) premultiply<N>(o, Q);
-  }
-  if (lane == 0 && agg_out) store_mat<N>(agg_out, Q);
+  Mat<N> P;
+  lane_scan<N, E>(M, n, base, lane, P);
+  if (lane == 63 && agg_out) store_mat<N>(agg_out, P);
 }
 
 // Tile apply: before[i] = M[i-1] ... M[tT] start for i in tile t (the state
@@ -80,16 +114,7 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
                                            double* __restrict__ spin = nullptr) {
   const int64_t base = tile * (64 * E) + (int64_t)lane * E;
   Mat<N> P;
-  lane_product<N, E>(M, n, base, P);
-  // inclusive scan over lanes: P_lane = Q_lane ... Q_0
-  for (int d = 1; d < 64; d <<= 1) {
-    const Mat<N> o = shfl_up_mat<N>(P, d);
-    if (lane >= d) {
-      Mat<N> t;
-      matmul<N>(P, o, t);
-      P = t;
-    }
-  }
+  lane_scan<N, E>(M, n, base, lane, P);
   Mat<N> X = shfl_up_mat<N>(P, 1);
   if (lane == 0) set_identity<N>(X);
   if (!valid) return;

@@ -3,7 +3,7 @@ result of the batch plan's segmented scan on the same operators, within
 rounding of the oracle's sequential product, and bitwise repeatable through
 one workspace and in replays of a captured graph.  Shapes cover one level
 above the operators (K <= 65536), two levels with the upper two in one
-workgroup (at most 16 level-1 tiles) and beyond it, and three levels."""
+workgroup (at most 8 level-1 tiles) and beyond it, and three levels."""
 import numpy as np
 import pytest
 
@@ -12,8 +12,8 @@ from paper_2204_05586_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(2, 257), (3, 3000), (2, 10_000), (3, 65_536), (3, 65_537), (2, 200_000),
-          (3, 200_000), (3, 262_144), (3, 262_145), (2, 458_752), (3, 1 << 20),
-          (2, (1 << 20) + 1)]
+          (3, 200_000), (3, 262_144), (3, 262_145), (2, 458_752), (3, 524_288),
+          (2, 524_289), (3, 1 << 20), (2, (1 << 20) + 1)]
 
 
 @pytest.fixture(scope="module")
