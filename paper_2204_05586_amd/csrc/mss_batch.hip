@@ -218,7 +218,7 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
   if (P->work.chained) {
     // unit tags are unit + 1 in 32 bits
     for (int i = 0; i < n; ++i) {
-      const int64_t per = 64 >> P->work.sims[i].slices_log2;
+      const int64_t per = (int64_t)kChainPerLane * (64 >> P->work.sims[i].slices_log2);
       if ((problems[i].n_samples + per - 1) / per >= ((int64_t)1 << 31)) {
         release(P);
         return api_fail(MSS_E_UNSUPPORTED, "simulation %d is too long for a chained plan", i);
@@ -240,7 +240,8 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
                        P->o_apply, P->o_chain);
   const int wps = opt.waves_per_simd ? opt.waves_per_simd : 2;
   const int64_t blocks = (int64_t)cu * wps;  // 256-thread blocks: one wave per SIMD each
-  P->grid_blocks = (int)std::max<int64_t>(1, std::min(blocks, (P->work.n_items + 3) / 4));
+  const int64_t units = P->work.chained ? P->work.n_units : P->work.n_items;
+  P->grid_blocks = (int)std::max<int64_t>(1, std::min(blocks, (units + 3) / 4));
   *out = P;
   return api_ok();
 }
@@ -290,7 +291,7 @@ mss_status mss_batch_workspace_size(const mss_batch_plan* P, int32_t store_u, si
 mss_status mss_batch_info(const mss_batch_plan* P, mss_batch_info_t* info) {
   if (!P || !info) return api_fail(MSS_E_INVALID, "plan and info are required");
   info->n_sims = P->n;
-  info->n_items = P->work.n_items;
+  info->n_items = P->work.chained ? P->work.n_units : P->work.n_items;
   info->grid_blocks = P->grid_blocks;
   info->scan_levels = P->work.n_levels + 1;
   info->pad = 0;

@@ -105,6 +105,25 @@ __device__ __forceinline__ void premultiply(const Mat<N>& A, Mat<N>& M) {
   M = t;
 }
 
+// y = M x for a complex N x N matrix and an N-vector (re / im parts apart).
+template <int N>
+__device__ __forceinline__ void matvec(const Mat<N>& M, const double* xr, const double* xi,
+                                       double* yr, double* yi) {
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      re = fma(M.r[a][b], xr[b], re);
+      re = fma(-M.i[a][b], xi[b], re);
+      im = fma(M.r[a][b], xi[b], im);
+      im = fma(M.i[a][b], xr[b], im);
+    }
+    yr[a] = re;
+    yi[a] = im;
+  }
+}
+
 template <int N>
 __device__ __forceinline__ Mat<N> shfl_down_mat(const Mat<N>& m, int d) {
   Mat<N> o;

@@ -33,25 +33,6 @@ __device__ __forceinline__ void project_spin(const double* vr, const double* vi,
   j3[2] = jz;
 }
 
-// y = M x for a complex N x N matrix and an N-vector (re / im parts apart).
-template <int N>
-__device__ __forceinline__ void matvec(const Mat<N>& M, const double* xr, const double* xi,
-                                       double* yr, double* yi) {
-#pragma unroll
-  for (int a = 0; a < N; ++a) {
-    double re = 0.0, im = 0.0;
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      re = fma(M.r[a][b], xr[b], re);
-      re = fma(-M.i[a][b], xi[b], re);
-      im = fma(M.r[a][b], xi[b], im);
-      im = fma(M.i[a][b], xr[b], im);
-    }
-    yr[a] = re;
-    yi[a] = im;
-  }
-}
-
 // Product of the lane's (up to) E consecutive matrices, later on the left
 // (the identity for a lane past the end).  The first matrix is loaded as
 // the start value: multiplying it into the identity would give the same

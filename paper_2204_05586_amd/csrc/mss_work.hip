@@ -208,14 +208,14 @@ void WorkSet::finalize() {
   }
   n_items = item;
   if (chained) {
-    // unit counts per sequence (64 / S intervals each), sequences by
-    // decreasing count; walking from the shortest up, each new count starts
-    // a group of rounds in which exactly the sequences before it (in
-    // `order`) and itself take part
+    // unit counts per sequence (kChainPerLane 64 / S intervals each),
+    // sequences by decreasing count; walking from the shortest up, each new
+    // count starts a group of rounds in which exactly the sequences before
+    // it (in `order`) and itself take part
     std::vector<int64_t> cnt(n);
     n_units = 0;
     for (int i = 0; i < n; ++i) {
-      const int64_t per = 64 >> sims[i].slices_log2;
+      const int64_t per = (int64_t)kChainPerLane * (64 >> sims[i].slices_log2);
       cnt[i] = (sims[i].k_count + per - 1) / per;
       n_units += cnt[i];
     }

@@ -214,25 +214,58 @@ __device__ __forceinline__ void chain_send(ChainSlot* slot, unsigned tag, int la
                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One chained unit: the 64 / S consecutive intervals of one simulation
-// from interval unit * 64 / S on.  The operators (written to U when the
-// descriptor has one), their ordered products within the wave, the entering
-// state (psi0 for the simulation's first unit, otherwise the state the unit
-// before left in the slot) and every interval's entering state; the state
-// leaving the unit goes to the slot, or to psi_final after the
-// simulation's last interval.  Every branch on the unit's shape is
-// wave-uniform.
+// Intervals per lane group in a chained unit: a unit is 64 / S groups of
+// kChainPerLane consecutive intervals.  Two halve the unit's scan and
+// hand-off per interval; the group's first operator waits in LDS while the
+// second is integrated, so the integration needs no more registers.
+constexpr int kChainPerLane = 2;
+
+// LDS a chained unit parks one operator in: 2 N^2 doubles per lane, element
+// e of lane l at [e * 64 + l] (64 consecutive doubles per element, no bank
+// conflicts).
+template <int N>
+__device__ __forceinline__ void park_mat(double* __restrict__ lds, int lane, const Mat<N>& m) {
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      lds[(2 * (a * N + b)) * 64 + lane] = m.r[a][b];
+      lds[(2 * (a * N + b) + 1) * 64 + lane] = m.i[a][b];
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void unpark_mat(const double* __restrict__ lds, int lane, Mat<N>& m) {
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      m.r[a][b] = lds[(2 * (a * N + b)) * 64 + lane];
+      m.i[a][b] = lds[(2 * (a * N + b) + 1) * 64 + lane];
+    }
+}
+
+// One chained unit: 64 / S groups of two consecutive intervals of one
+// simulation, from interval 2 unit * 64 / S on; lanes jS .. jS + S - 1 form
+// group j.  The operators (written to U when the descriptor has one), the
+// group products Q_j = U_{2j+1} U_{2j}, their ordered products within the
+// wave, the entering state (psi0 for the simulation's first unit, otherwise
+// the state the unit before left in the slot) and every interval's entering
+// state; the state leaving the unit goes to the slot, or to psi_final after
+// the simulation's last interval.  Every branch on the unit's shape is
+// wave-uniform.  lds: this wave's 2 N^2 x 64 doubles.
 template <int N, class Source>
 __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const SimDesc& s,
                                              ChainSlot* slot, int64_t unit, int lane,
-                                             const Source& source) {
+                                             double* __restrict__ lds, const Source& source) {
+  static_assert(kChainPerLane == 2, "a group parks exactly one operator");
   const int sl = s.slices_log2;
-  const int per = 64 >> sl;
-  const int jl = lane >> sl;  // interval within the unit
+  const int per = 64 >> sl;   // groups in the unit
+  const int jl = lane >> sl;  // this lane's group
   const int slice = lane & ((1 << sl) - 1);
-  const int64_t kb = unit * per;
-  const int64_t k = kb + jl;
-  const bool active = k < s.K_total;
+  const int64_t span = (int64_t)per * kChainPerLane;
+  const int64_t kb = unit * span;
+  const int64_t k0 = kb + (int64_t)jl * kChainPerLane;  // the group's first interval
   using Terms = decltype(source(A, s));
   // the state the unit before left is read now: with a round's units spread
   // over the queue it is usually there already, and the read's round trip
@@ -240,25 +273,41 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
   const bool first = wave_uniform(unit == 0);
   unsigned long long early = 0ull;
   if (!first && lane < 4 * N) early = chain_read(&slot->w[lane]);
-  Mat<N> P;
-  double tk;
-  bool done = false;
-  if constexpr (N == 3 && has_full_basis<Terms>::value) {
-    if (s.full) {
-      interval_operator<3, true, true>(source(A, s), s.params, s.t_start, s.dt_out, s.dt,
-                                       s.n_fine, s.tau, s.frame, s.method, k, slice, sl, active,
-                                       P, &tk);
-      done = true;
+  // Q_j = U_{k0+1} U_{k0}: U_{k0} is parked while U_{k0+1} is integrated (one
+  // copy of the integration code: the loop is not unrolled), so that nothing
+  // but the parked operator outlives an integration
+  Mat<N> U;
+#pragma unroll 1
+  for (int e = 0;; ++e) {
+    const int64_t k = k0 + e;
+    const bool active = k < s.K_total;
+    double tk;
+    bool done = false;
+    if constexpr (N == 3 && has_full_basis<Terms>::value) {
+      if (s.full) {
+        interval_operator<3, true, true>(source(A, s), s.params, s.t_start, s.dt_out, s.dt,
+                                         s.n_fine, s.tau, s.frame, s.method, k, slice, sl,
+                                         active, U, &tk);
+        done = true;
+      }
     }
+    if (!done)
+      interval_operator<N, false, true>(source(A, s), s.params, s.t_start, s.dt_out, s.dt,
+                                        s.n_fine, s.tau, s.frame, s.method, k, slice, sl,
+                                        active, U, &tk);
+    if (active && slice == 0 && s.U) store_mat<N>(s.U + (size_t)k * 2 * N * N, U);
+    if (!active) set_identity<N>(U);
+    if (e + 1 == kChainPerLane) break;
+    park_mat<N>(lds, lane, U);
   }
-  if (!done)
-    interval_operator<N, false, true>(source(A, s), s.params, s.t_start, s.dt_out, s.dt,
-                                      s.n_fine, s.tau, s.frame, s.method, k, slice, sl, active,
-                                      P, &tk);
-  if (active && slice == 0 && s.U) store_mat<N>(s.U + (size_t)k * 2 * N * N, P);
-  if (!active) set_identity<N>(P);
-  // P_j = U_j ... U_0 over the unit's intervals (lanes with slice 0; the
-  // other lanes compute values nobody reads)
+  Mat<N> P;
+  {
+    Mat<N> U0;
+    unpark_mat<N>(lds, lane, U0);
+    matmul<N>(U, U0, P);
+  }
+  // P_j = Q_j ... Q_0 over the unit's groups (lanes with slice 0; the other
+  // lanes compute values nobody reads)
   for (int d = 1; d < per; d <<= 1) {
     const Mat<N> o = shfl_up_mat<N>(P, d << sl);
     if (jl >= d) {
@@ -278,22 +327,11 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
   } else {
     (void)chain_receive<N>(slot, (unsigned)unit, A.sync, lane, early, xr, xi);
   }
-  // y = P_j x: the state leaving interval j; the one entering it is the
-  // previous interval's leaving state (x for the first)
+  // y = P_j x: the state leaving group j; the one entering it is the group
+  // before's leaving state (x for the first), and U_{k0} of that the state
+  // entering the group's second interval
   double yr[N], yi[N];
-#pragma unroll
-  for (int a = 0; a < N; ++a) {
-    double re = 0.0, im = 0.0;
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-      re = fma(P.r[a][b], xr[b], re);
-      re = fma(-P.i[a][b], xi[b], re);
-      im = fma(P.r[a][b], xi[b], im);
-      im = fma(P.i[a][b], xr[b], im);
-    }
-    yr[a] = re;
-    yi[a] = im;
-  }
+  matvec<N>(P, xr, xi, yr, yi);
   double er[N], ei[N];
 #pragma unroll
   for (int a = 0; a < N; ++a) {
@@ -304,17 +342,32 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
       ei[a] = xi[a];
     }
   }
-  if (active && slice == 0) {
-    double* o = s.psi + (size_t)k * 2 * N;
+  double fr[N], fi[N];
+  {
+    Mat<N> U0;
+    unpark_mat<N>(lds, lane, U0);
+    matvec<N>(U0, er, ei, fr, fi);
+  }
+  if (slice == 0) {
+    double* o = s.psi + (size_t)k0 * 2 * N;
+    if (k0 < s.K_total) {
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
-      o[2 * a] = er[a];
-      o[2 * a + 1] = ei[a];
+      for (int a = 0; a < N; ++a) {
+        o[2 * a] = er[a];
+        o[2 * a + 1] = ei[a];
+      }
+    }
+    if (k0 + 1 < s.K_total) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        o[2 * N + 2 * a] = fr[a];
+        o[2 * N + 2 * a + 1] = fi[a];
+      }
     }
   }
-  // the state leaving the unit: that of its last interval's lane
-  const int64_t n_here = s.K_total - kb < per ? s.K_total - kb : per;
-  const int last = ((int)n_here - 1) << sl;
+  // the state leaving the unit: that of the group holding its last interval
+  const int64_t n_here = s.K_total - kb < span ? s.K_total - kb : span;
+  const int last = ((int)(n_here - 1) / kChainPerLane) << sl;
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     xr[a] = __shfl(yr[a], last, 64);
@@ -324,7 +377,7 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
   // conditions: an if / else-if with a one-lane branch here made the
   // compiler build the persistent loop as a divergent loop, in which a
   // wave could reach the next dequeue without lane 0 and run a unit twice.
-  const bool more = wave_uniform(kb + per < s.K_total);
+  const bool more = wave_uniform(kb + span < s.K_total);
   if (more) chain_send<N>(slot, (unsigned)(unit + 1), lane, xr, xi);
   double f = 0.0;
 #pragma unroll
@@ -343,6 +396,16 @@ template <class Source>
 __device__ __forceinline__ void chained_integrate_loop(const IntegrateWorkArgs& A,
                                                        const Source& source) {
   const int lane = threadIdx.x & 63;
+  // each wave's parking space for one operator per lane; the launches use
+  // 256-lane blocks, and a wider one fails the run instead of overrunning it
+  __shared__ double park[4 * 2 * 3 * 3 * 64];
+  if (blockDim.x > 256) {
+    if (threadIdx.x == 0)
+      (void)__hip_atomic_exchange(&A.sync->failed, ~0ull, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  double* lds = park + (threadIdx.x >> 6) * (2 * 3 * 3 * 64);
   int64_t item = 0;
   if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
   item = wave_broadcast(item);
@@ -372,8 +435,8 @@ __device__ __forceinline__ void chained_integrate_loop(const IntegrateWorkArgs& 
     const int64_t round = wave_broadcast(A.group_round0[lo] + off / cnt);
     const int sim = __builtin_amdgcn_readfirstlane(A.order[off % cnt]);
     const SimDesc& s = A.sims[sim];
-    if (s.spin_twice == 2) chained_unit<3>(A, s, A.slots + sim, round, lane, source);
-    else chained_unit<2>(A, s, A.slots + sim, round, lane, source);
+    if (s.spin_twice == 2) chained_unit<3>(A, s, A.slots + sim, round, lane, lds, source);
+    else chained_unit<2>(A, s, A.slots + sim, round, lane, lds, source);
     if (!ahead && lane == 0) next = (int64_t)atomicAdd(A.counter, 1ull);
     item = wave_broadcast(next);
   }
