@@ -331,7 +331,7 @@ typedef struct mss_batch_options {
                                buffer pointers stay the same */
   int32_t scan_per_lane;    /* operators per lane in the scan tiles: 2, 4 or 8 (0: 4) */
   int32_t chained;          /* 1: mss_batch_run forms the states inside the integrator's
-                               launch: each unit (2 x 64 / S consecutive intervals, one wave)
+                               launch: each unit (3 x 64 / S consecutive intervals, one wave)
                                multiplies its operators together in registers and passes its
                                leaving state to the next unit of its simulation, units being
                                taken round by round across the simulations; no operator
@@ -347,7 +347,7 @@ typedef struct mss_batch_info_t {
   int32_t grid_blocks;      /* 256-thread workgroups of the persistent integrator */
   int32_t pad;
   int64_t n_items;          /* work items (one wave's worth of intervals each; in a chained
-                               plan the units, 2 x 64 / S intervals each) */
+                               plan the units, 3 x 64 / S intervals each) */
   int64_t total_samples;    /* sum of K_i */
 } mss_batch_info_t;
 

@@ -215,14 +215,15 @@ __device__ __forceinline__ void chain_send(ChainSlot* slot, unsigned tag, int la
 }
 
 // Intervals per lane group in a chained unit: a unit is 64 / S groups of
-// kChainPerLane consecutive intervals.  Two halve the unit's scan and
-// hand-off per interval; the group's first operator waits in LDS while the
-// second is integrated, so the integration needs no more registers.
-constexpr int kChainPerLane = 2;
+// kChainPerLane consecutive intervals.  More than one cuts the unit's scan
+// and hand-off per interval; a group's earlier operators wait in LDS while
+// the last is integrated, so the integration needs no more registers.
+constexpr int kChainPerLane = 3;
+// doubles of LDS per wave for the parked operators (spin-1 size)
+constexpr int kChainParkDoubles = (kChainPerLane - 1) * 2 * 3 * 3 * 64;
 
-// LDS a chained unit parks one operator in: 2 N^2 doubles per lane, element
-// e of lane l at [e * 64 + l] (64 consecutive doubles per element, no bank
-// conflicts).
+// A parked operator in LDS: 2 N^2 doubles per lane, element e of lane l at
+// [e * 64 + l] (64 consecutive doubles per element, no bank conflicts).
 template <int N>
 __device__ __forceinline__ void park_mat(double* __restrict__ lds, int lane, const Mat<N>& m) {
 #pragma unroll
@@ -245,27 +246,29 @@ __device__ __forceinline__ void unpark_mat(const double* __restrict__ lds, int l
     }
 }
 
-// One chained unit: 64 / S groups of two consecutive intervals of one
-// simulation, from interval 2 unit * 64 / S on; lanes jS .. jS + S - 1 form
-// group j.  The operators (written to U when the descriptor has one), the
-// group products Q_j = U_{2j+1} U_{2j}, their ordered products within the
-// wave, the entering state (psi0 for the simulation's first unit, otherwise
-// the state the unit before left in the slot) and every interval's entering
-// state; the state leaving the unit goes to the slot, or to psi_final after
-// the simulation's last interval.  Every branch on the unit's shape is
-// wave-uniform.  lds: this wave's 2 N^2 x 64 doubles.
+// One chained unit: 64 / S groups of E = kChainPerLane consecutive
+// intervals of one simulation, from interval E unit 64 / S on; lanes
+// jS .. jS + S - 1 form group j.  The operators (written to U when the
+// descriptor has one), the group products Q_j = U_{Ej+E-1} ... U_{Ej}, their
+// ordered products within the wave, the entering state (psi0 for the
+// simulation's first unit, otherwise the state the unit before left in the
+// slot) and every interval's entering state; the state leaving the unit
+// goes to the slot, or to psi_final after the simulation's last interval.
+// Every branch on the unit's shape is wave-uniform.  lds: this wave's
+// kChainParkDoubles doubles.
 template <int N, class Source>
 __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const SimDesc& s,
                                              ChainSlot* slot, int64_t unit, int lane,
                                              double* __restrict__ lds, const Source& source) {
-  static_assert(kChainPerLane == 2, "a group parks exactly one operator");
+  constexpr int E = kChainPerLane;
+  constexpr int kPark = 2 * N * N * 64;  // doubles per parked operator
   const int sl = s.slices_log2;
   const int per = 64 >> sl;   // groups in the unit
   const int jl = lane >> sl;  // this lane's group
   const int slice = lane & ((1 << sl) - 1);
-  const int64_t span = (int64_t)per * kChainPerLane;
+  const int64_t span = (int64_t)per * E;
   const int64_t kb = unit * span;
-  const int64_t k0 = kb + (int64_t)jl * kChainPerLane;  // the group's first interval
+  const int64_t k0 = kb + (int64_t)jl * E;  // the group's first interval
   using Terms = decltype(source(A, s));
   // the state the unit before left is read now: with a round's units spread
   // over the queue it is usually there already, and the read's round trip
@@ -273,9 +276,10 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
   const bool first = wave_uniform(unit == 0);
   unsigned long long early = 0ull;
   if (!first && lane < 4 * N) early = chain_read(&slot->w[lane]);
-  // Q_j = U_{k0+1} U_{k0}: U_{k0} is parked while U_{k0+1} is integrated (one
-  // copy of the integration code: the loop is not unrolled), so that nothing
-  // but the parked operator outlives an integration
+  // Q_j = U_{k0+E-1} ... U_{k0}: each operator but the last is parked while
+  // the next is integrated (one copy of the integration code: the loop is
+  // not unrolled), so that nothing but parked operators outlives an
+  // integration
   Mat<N> U;
 #pragma unroll 1
   for (int e = 0;; ++e) {
@@ -297,14 +301,16 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
                                         active, U, &tk);
     if (active && slice == 0 && s.U) store_mat<N>(s.U + (size_t)k * 2 * N * N, U);
     if (!active) set_identity<N>(U);
-    if (e + 1 == kChainPerLane) break;
-    park_mat<N>(lds, lane, U);
+    if (e + 1 == E) break;
+    park_mat<N>(lds + e * kPark, lane, U);
   }
-  Mat<N> P;
-  {
-    Mat<N> U0;
-    unpark_mat<N>(lds, lane, U0);
-    matmul<N>(U, U0, P);
+  Mat<N> P = U;
+#pragma unroll
+  for (int e = E - 2; e >= 0; --e) {
+    Mat<N> Ue, t;
+    unpark_mat<N>(lds + e * kPark, lane, Ue);
+    matmul<N>(P, Ue, t);
+    P = t;
   }
   // P_j = Q_j ... Q_0 over the unit's groups (lanes with slice 0; the other
   // lanes compute values nobody reads)
@@ -328,8 +334,8 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
     (void)chain_receive<N>(slot, (unsigned)unit, A.sync, lane, early, xr, xi);
   }
   // y = P_j x: the state leaving group j; the one entering it is the group
-  // before's leaving state (x for the first), and U_{k0} of that the state
-  // entering the group's second interval
+  // before's leaving state (x for the first), and the parked operators
+  // carry it through the group's earlier intervals
   double yr[N], yi[N];
   matvec<N>(P, xr, xi, yr, yi);
   double er[N], ei[N];
@@ -342,32 +348,31 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
       ei[a] = xi[a];
     }
   }
-  double fr[N], fi[N];
-  {
-    Mat<N> U0;
-    unpark_mat<N>(lds, lane, U0);
-    matvec<N>(U0, er, ei, fr, fi);
-  }
-  if (slice == 0) {
-    double* o = s.psi + (size_t)k0 * 2 * N;
-    if (k0 < s.K_total) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (slice == 0 && k0 + e < s.K_total) {
+      double* o = s.psi + (size_t)(k0 + e) * 2 * N;
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         o[2 * a] = er[a];
         o[2 * a + 1] = ei[a];
       }
     }
-    if (k0 + 1 < s.K_total) {
+    if (e + 1 < E) {
+      Mat<N> Ue;
+      unpark_mat<N>(lds + e * kPark, lane, Ue);
+      double fr[N], fi[N];
+      matvec<N>(Ue, er, ei, fr, fi);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
-        o[2 * N + 2 * a] = fr[a];
-        o[2 * N + 2 * a + 1] = fi[a];
+        er[a] = fr[a];
+        ei[a] = fi[a];
       }
     }
   }
   // the state leaving the unit: that of the group holding its last interval
   const int64_t n_here = s.K_total - kb < span ? s.K_total - kb : span;
-  const int last = ((int)(n_here - 1) / kChainPerLane) << sl;
+  const int last = ((int)(n_here - 1) / E) << sl;
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     xr[a] = __shfl(yr[a], last, 64);
@@ -396,16 +401,16 @@ template <class Source>
 __device__ __forceinline__ void chained_integrate_loop(const IntegrateWorkArgs& A,
                                                        const Source& source) {
   const int lane = threadIdx.x & 63;
-  // each wave's parking space for one operator per lane; the launches use
+  // each wave's parking space for its lanes' parked operators; the launches use
   // 256-lane blocks, and a wider one fails the run instead of overrunning it
-  __shared__ double park[4 * 2 * 3 * 3 * 64];
+  __shared__ double park[4 * kChainParkDoubles];
   if (blockDim.x > 256) {
     if (threadIdx.x == 0)
       (void)__hip_atomic_exchange(&A.sync->failed, ~0ull, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
-  double* lds = park + (threadIdx.x >> 6) * (2 * 3 * 3 * 64);
+  double* lds = park + (threadIdx.x >> 6) * kChainParkDoubles;
   int64_t item = 0;
   if (lane == 0) item = (int64_t)atomicAdd(A.counter, 1ull);
   item = wave_broadcast(item);
