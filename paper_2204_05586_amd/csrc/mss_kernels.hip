@@ -36,8 +36,9 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const double* __restric
   const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t ntiles = (n + kScanTile - 1) / kScanTile;
   const bool valid = tile < ntiles;
-  tile_apply<N, kScanPerLane>(M, n, tile, lane, valid, valid ? start + (size_t)tile * 2 * N : nullptr, before,
-                after_last, spin);
+  tile_apply<N, kScanPerLane, true>(M, n, tile, lane, valid,
+                                    valid ? start + (size_t)tile * 2 * N : nullptr, before,
+                                    after_last, spin);
 }
 
 // Levels 1 and 2 of a two-level scan in one workgroup (n1 <= kTopWaves tiles of

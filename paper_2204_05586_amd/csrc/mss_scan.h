@@ -53,13 +53,25 @@ __device__ __forceinline__ void lane_product(const double* __restrict__ M, int64
   }
 }
 
-// Inclusive products over a tile: lane j ends with P_j = Q_j ... Q_0, Q_j
-// the product of its E elements (a six-level shuffle scan).  Every lane
-// must call this.
+// The lane's (up to) E consecutive matrices kept in X, and their product as
+// lane_product forms it (the same operations in the same order).
 template <int N, int E>
-__device__ __forceinline__ void lane_scan(const double* __restrict__ M, int64_t n, int64_t base,
-                                          int lane, Mat<N>& P) {
-  lane_product<N, E>(M, n, base, P);
+__device__ __forceinline__ void lane_product_keep(const double* __restrict__ M, int64_t n,
+                                                  int64_t base, Mat<N>& Q, Mat<N> (&X)[E]) {
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (base + e < n) load_mat<N>(M + (size_t)(base + e) * 2 * N * N, X[e]);
+  if (base < n) Q = X[0];
+  else set_identity<N>(Q);
+#pragma unroll
+  for (int e = 1; e < E; ++e)
+    if (base + e < n) premultiply<N>(X[e], Q);
+}
+
+// Inclusive products over the wave: lane j's P (its Q_j on entry) becomes
+// P_j = Q_j ... Q_0 (a six-level shuffle scan).
+template <int N>
+__device__ __forceinline__ void wave_scan(int lane, Mat<N>& P) {
   for (int d = 1; d < 64; d <<= 1) {
     const Mat<N> o = shfl_up_mat<N>(P, d);
     if (lane >= d) {
@@ -68,6 +80,15 @@ __device__ __forceinline__ void lane_scan(const double* __restrict__ M, int64_t 
       P = t;
     }
   }
+}
+
+// Inclusive products over a tile: lane j ends with P_j = Q_j ... Q_0, Q_j
+// the product of its E elements.  Every lane must call this.
+template <int N, int E>
+__device__ __forceinline__ void lane_scan(const double* __restrict__ M, int64_t n, int64_t base,
+                                          int lane, Mat<N>& P) {
+  lane_product<N, E>(M, n, base, P);
+  wave_scan<N>(lane, P);
 }
 
 // Tile reduce: agg = M[tT + T - 1] ... M[tT] of tile t (T = 64 E), one
@@ -87,7 +108,9 @@ __device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_
 // entering element i); after_last (optional) receives M[n-1] ... applied
 // when the tile holds the last element; spin (optional, [n][3]) receives
 // <J_x>, <J_y>, <J_z> of every state written.  Every lane must call this.
-template <int N, int E>
+// KEEP: the lane's matrices stay in registers from the scan to the walk
+// (one read of M instead of two); the values and operations are the same.
+template <int N, int E, bool KEEP = false>
 __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t n, int64_t tile,
                                            int lane, bool valid, const double* __restrict__ start,
                                            double* __restrict__ before,
@@ -95,7 +118,10 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
                                            double* __restrict__ spin = nullptr) {
   const int64_t base = tile * (64 * E) + (int64_t)lane * E;
   Mat<N> P;
-  lane_scan<N, E>(M, n, base, lane, P);
+  Mat<N> kept[KEEP ? E : 1];
+  if constexpr (KEEP) lane_product_keep<N, E>(M, n, base, P, kept);
+  else lane_product<N, E>(M, n, base, P);
+  wave_scan<N>(lane, P);
   Mat<N> X = shfl_up_mat<N>(P, 1);
   if (lane == 0) set_identity<N>(X);
   if (!valid) return;
@@ -134,7 +160,8 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
       }
       if (spin) project_spin<N>(vr, vi, spin + 3 * idx);
       Mat<N> Y;
-      load_mat<N>(M + (size_t)idx * 2 * N * N, Y);
+      if constexpr (KEEP) Y = kept[e];
+      else load_mat<N>(M + (size_t)idx * 2 * N * N, Y);
       double wr_[N], wi_[N];
 #pragma unroll
       for (int a = 0; a < N; ++a) {

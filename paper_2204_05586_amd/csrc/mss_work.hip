@@ -134,7 +134,8 @@ __device__ __forceinline__ void work_apply_tile(const SimDesc& s, int level, int
     const int64_t n_up = level_geometry<N, E>(s, level + 1, &up_off);
     start = s.scan_ws + up_off + (size_t)n_up * 2 * N * N + (size_t)local * 2 * N;
   }
-  tile_apply<N, E>(M, n, local, lane, true, start, before, level == 0 ? s.psi_final : nullptr);
+  tile_apply<N, E, (E * 2 * N * N <= 36)>(M, n, local, lane, true, start, before,
+                                           level == 0 ? s.psi_final : nullptr);
 }
 
 template <int E>
