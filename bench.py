@@ -43,14 +43,14 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # the sources are unchanged.
 MEASURED_TRAFFIC = {
     ("mss_user_work_chained", "batched_sensing"): {
-        "src": "d1cab8ae5482b759",
-        "fetch_kib": 496467.3, "write_kib": 25013906.3,
-        "bytes": int(round((496467.3 * 2.000 + 25013906.3 * 1.000) * 1024)),
+        "src": "7d82bdc268f96482",
+        "fetch_kib": 295194.3, "write_kib": 25472534.4,
+        "bytes": int(round((295194.3 * 2.000 + 25472534.4 * 1.000) * 1024)),
     },
     ("mss_user_work_integrate", "batched_sensing"): {
-        "src": "d1cab8ae5482b759",
-        "fetch_kib": 3781.1, "write_kib": 64036183.8,
-        "bytes": int(round((3781.1 * 2.000 + 64036183.8 * 1.000) * 1024)),
+        "src": "7d82bdc268f96482",
+        "fetch_kib": 3723.7, "write_kib": 64036093.9,
+        "bytes": int(round((3723.7 * 2.000 + 64036093.9 * 1.000) * 1024)),
     },
 }
 
