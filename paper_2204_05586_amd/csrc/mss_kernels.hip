@@ -62,9 +62,10 @@ __global__ void __launch_bounds__(64 * kTopWaves) scan_top_kernel(const double* 
   const int wave = threadIdx.x >> 6;
   const int64_t n2 = blockDim.x >> 6;
   const int64_t base = (int64_t)wave * kScanTile + (int64_t)lane * E;
+  const int L = lanes_with_data<E>(n1, wave);
   Mat<N> P;
-  lane_scan<N, E>(M1, n1, base, lane, P);
-  if (lane == 63) store_mat<N>(total + (size_t)wave * 2 * N * N, P);
+  lane_scan<N, E>(M1, n1, base, lane, L, P);
+  if (lane == L - 1) store_mat<N>(total + (size_t)wave * 2 * N * N, P);
   __syncthreads();
   if (wave == 0) tile_apply<N, E>(total, n2, 0, lane, true, start, enter, nullptr);
   __syncthreads();

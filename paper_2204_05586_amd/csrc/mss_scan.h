@@ -68,11 +68,22 @@ __device__ __forceinline__ void lane_product_keep(const double* __restrict__ M, 
     if (base + e < n) premultiply<N>(X[e], Q);
 }
 
-// Inclusive products over the wave: lane j's P (its Q_j on entry) becomes
-// P_j = Q_j ... Q_0 (a six-level shuffle scan).
+// Lanes of tile t that hold elements (n elements in all): wave-uniform, at
+// most 64, 0 or less past the last tile.
+template <int E>
+__device__ __forceinline__ int lanes_with_data(int64_t n, int64_t tile) {
+  const int64_t left = n - tile * (64 * E);
+  return left >= 64 * E ? 64 : (int)((left + E - 1) / E);
+}
+
+// Inclusive products over the wave's first L lanes: lane j's P (its Q_j on
+// entry) becomes P_j = Q_j ... Q_0 for j < L, by shuffle levels of stride
+// 1, 2, 4, ... below L (a level of stride L or more changes no lane below
+// L, so stopping there gives those lanes the values the full six levels
+// give).  L is wave-uniform.
 template <int N>
-__device__ __forceinline__ void wave_scan(int lane, Mat<N>& P) {
-  for (int d = 1; d < 64; d <<= 1) {
+__device__ __forceinline__ void wave_scan(int lane, int L, Mat<N>& P) {
+  for (int d = 1; d < L; d <<= 1) {
     const Mat<N> o = shfl_up_mat<N>(P, d);
     if (lane >= d) {
       Mat<N> t;
@@ -82,26 +93,27 @@ __device__ __forceinline__ void wave_scan(int lane, Mat<N>& P) {
   }
 }
 
-// Inclusive products over a tile: lane j ends with P_j = Q_j ... Q_0, Q_j
-// the product of its E elements.  Every lane must call this.
+// Inclusive products over a tile: lane j < L ends with P_j = Q_j ... Q_0,
+// Q_j the product of its E elements.  Every lane must call this.
 template <int N, int E>
 __device__ __forceinline__ void lane_scan(const double* __restrict__ M, int64_t n, int64_t base,
-                                          int lane, Mat<N>& P) {
+                                          int lane, int L, Mat<N>& P) {
   lane_product<N, E>(M, n, base, P);
-  wave_scan<N>(lane, P);
+  wave_scan<N>(lane, L, P);
 }
 
 // Tile reduce: agg = M[tT + T - 1] ... M[tT] of tile t (T = 64 E), one
-// wave per tile: the last lane's inclusive product, so that a tile's
-// aggregate is bit for bit the total that tile_apply's scan forms.  M
-// points at element 0 of the sequence, n its length.
+// wave per tile: the inclusive product of the last lane holding elements,
+// so that a tile's aggregate is bit for bit the total that tile_apply's
+// scan forms.  M points at element 0 of the sequence, n its length.
 template <int N, int E>
 __device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_t n, int64_t tile,
                                             int lane, double* __restrict__ agg_out) {
   const int64_t base = tile * (64 * E) + (int64_t)lane * E;
+  const int L = lanes_with_data<E>(n, tile);
   Mat<N> P;
-  lane_scan<N, E>(M, n, base, lane, P);
-  if (lane == 63 && agg_out) store_mat<N>(agg_out, P);
+  lane_scan<N, E>(M, n, base, lane, L, P);
+  if (lane == L - 1 && agg_out) store_mat<N>(agg_out, P);
 }
 
 // Tile apply: before[i] = M[i-1] ... M[tT] start for i in tile t (the state
@@ -121,7 +133,7 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
   Mat<N> kept[KEEP ? E : 1];
   if constexpr (KEEP) lane_product_keep<N, E>(M, n, base, P, kept);
   else lane_product<N, E>(M, n, base, P);
-  wave_scan<N>(lane, P);
+  wave_scan<N>(lane, lanes_with_data<E>(n, tile), P);
   Mat<N> X = shfl_up_mat<N>(P, 1);
   if (lane == 0) set_identity<N>(X);
   if (!valid) return;
