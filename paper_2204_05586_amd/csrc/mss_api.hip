@@ -304,6 +304,14 @@ mss_status propagate(int32_t spin_twice, int64_t n_samples, const double* U, con
     if (e != hipSuccess) return api_hip_fail(e, "scan launch");
     return api_ok();
   }
+  if (lv.n_levels == 1) {
+    // level 0 up, then level 0 down with the single level-1 tile folded in
+    e = launch_scan_reduce(N, M[0], lv.n[0], (double*)M[1], st);
+    if (e == hipSuccess)
+      e = launch_scan_apply_fold(N, M[0], lv.n[0], M[1], lv.n[1], psi0, psi, psi_final, st, spin);
+    if (e != hipSuccess) return api_hip_fail(e, "scan launch");
+    return api_ok();
+  }
   for (int l = 0; l < lv.n_levels; ++l) {
     e = launch_scan_reduce(N, M[l], lv.n[l], (double*)M[l + 1], st);
     if (e != hipSuccess) return api_hip_fail(e, "scan reduce launch");

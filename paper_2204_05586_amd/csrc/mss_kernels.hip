@@ -41,6 +41,28 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const double* __restric
                                     after_last, spin);
 }
 
+// Level 0 of a one-level scan (n1 <= kScanTile tile aggregates A1) with the
+// top level folded in: each wave forms the state entering its tile from
+// start as the level-1 apply would (single_tile_state, the same operations),
+// then applies its tile.  Bitwise the result of the two launches.
+template <int N>
+__global__ void __launch_bounds__(256) scan_apply_fold_kernel(const double* __restrict__ M,
+                                                              int64_t n,
+                                                              const double* __restrict__ A1,
+                                                              int64_t n1,
+                                                              const double* __restrict__ start,
+                                                              double* __restrict__ before,
+                                                              double* __restrict__ after_last,
+                                                              double* __restrict__ spin) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const bool valid = tile < n1;
+  double sr[N], si[N];
+  single_tile_state<N, kScanPerLane>(A1, n1, valid ? tile : 0, lane, start, sr, si);
+  tile_apply<N, kScanPerLane, true>(M, n, tile, lane, valid, nullptr, before, after_last, spin,
+                                    sr, si);
+}
+
 // Levels 1 and 2 of a two-level scan in one workgroup (n1 <= kTopWaves tiles of
 // kScanTile level-1 elements), with one scan pass per wave: wave w forms
 // the inclusive products P_j of its tile (lane_scan, as tile_reduce and
@@ -170,6 +192,20 @@ hipError_t launch_scan_apply(int N, const double* M, int64_t n, const double* st
   else
     hipLaunchKernelGGL(scan_apply_kernel<3>, grid, block, 0, st, M, n, start, before, after_last,
                        spin);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_apply_fold(int N, const double* M, int64_t n, const double* A1, int64_t n1,
+                                  const double* start, double* before, double* after_last,
+                                  hipStream_t st, double* spin) {
+  if (n1 != (n + kScanTile - 1) / kScanTile || n1 > kScanTile) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)scan_grid(n)), block(256);
+  if (N == 2)
+    hipLaunchKernelGGL(scan_apply_fold_kernel<2>, grid, block, 0, st, M, n, A1, n1, start, before,
+                       after_last, spin);
+  else
+    hipLaunchKernelGGL(scan_apply_fold_kernel<3>, grid, block, 0, st, M, n, A1, n1, start, before,
+                       after_last, spin);
   return hipGetLastError();
 }
 

@@ -119,7 +119,9 @@ __device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_
 // Tile apply: before[i] = M[i-1] ... M[tT] start for i in tile t (the state
 // entering element i); after_last (optional) receives M[n-1] ... applied
 // when the tile holds the last element; spin (optional, [n][3]) receives
-// <J_x>, <J_y>, <J_z> of every state written.  Every lane must call this.
+// <J_x>, <J_y>, <J_z> of every state written.  The start state is read from
+// start, or (start null) taken from start_r / start_i in registers.  Every
+// lane must call this.
 // KEEP: the lane's matrices stay in registers from the scan to the walk
 // (one read of M instead of two); the values and operations are the same.
 template <int N, int E, bool KEEP = false>
@@ -127,7 +129,9 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
                                            int lane, bool valid, const double* __restrict__ start,
                                            double* __restrict__ before,
                                            double* __restrict__ after_last,
-                                           double* __restrict__ spin = nullptr) {
+                                           double* __restrict__ spin = nullptr,
+                                           const double* start_r = nullptr,
+                                           const double* start_i = nullptr) {
   const int64_t base = tile * (64 * E) + (int64_t)lane * E;
   Mat<N> P;
   Mat<N> kept[KEEP ? E : 1];
@@ -143,22 +147,10 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
     double sr[N], si[N];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-      sr[a] = start[2 * a];
-      si[a] = start[2 * a + 1];
+      sr[a] = start ? start[2 * a] : start_r[a];
+      si[a] = start ? start[2 * a + 1] : start_i[a];
     }
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-      double re = 0.0, im = 0.0;
-#pragma unroll
-      for (int b = 0; b < N; ++b) {
-        re = fma(X.r[a][b], sr[b], re);
-        re = fma(-X.i[a][b], si[b], re);
-        im = fma(X.r[a][b], si[b], im);
-        im = fma(X.i[a][b], sr[b], im);
-      }
-      vr[a] = re;
-      vi[a] = im;
-    }
+    matvec<N>(X, sr, si, vr, vi);
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -175,19 +167,7 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
       if constexpr (KEEP) Y = kept[e];
       else load_mat<N>(M + (size_t)idx * 2 * N * N, Y);
       double wr_[N], wi_[N];
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-          re = fma(Y.r[a][b], vr[b], re);
-          re = fma(-Y.i[a][b], vi[b], re);
-          im = fma(Y.r[a][b], vi[b], im);
-          im = fma(Y.i[a][b], vr[b], im);
-        }
-        wr_[a] = re;
-        wi_[a] = im;
-      }
+      matvec<N>(Y, vr, vi, wr_, wi_);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         vr[a] = wr_[a];
@@ -201,6 +181,51 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
         }
       }
     }
+  }
+}
+
+// The state entering element w of a sequence of n <= 64 E elements that
+// starts from `start` (every lane gets it): what tile_apply writes for
+// element w of tile 0, by the same operations (scan, the lane's prefix
+// applied to start, its walk up to w).  Every lane must call this.
+template <int N, int E>
+__device__ __forceinline__ void single_tile_state(const double* __restrict__ M, int64_t n,
+                                                  int64_t w, int lane,
+                                                  const double* __restrict__ start, double* vr,
+                                                  double* vi) {
+  const int64_t base = (int64_t)lane * E;
+  Mat<N> P;
+  lane_product<N, E>(M, n, base, P);
+  wave_scan<N>(lane, lanes_with_data<E>(n, 0), P);
+  Mat<N> X = shfl_up_mat<N>(P, 1);
+  if (lane == 0) set_identity<N>(X);
+  double sr[N], si[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    sr[a] = start[2 * a];
+    si[a] = start[2 * a + 1];
+  }
+  double ur[N], ui[N];
+  matvec<N>(X, sr, si, ur, ui);
+  const int owner = (int)(w / E);
+  const int steps = (int)(w % E);
+  for (int e = 0; e < steps; ++e) {  // wave-uniform count
+    Mat<N> Y;
+    const int64_t idx = base + e;
+    if (idx < n) load_mat<N>(M + (size_t)idx * 2 * N * N, Y);
+    else set_identity<N>(Y);
+    double wr_[N], wi_[N];
+    matvec<N>(Y, ur, ui, wr_, wi_);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      ur[a] = wr_[a];
+      ui[a] = wi_[a];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    vr[a] = __shfl(ur[a], owner, 64);
+    vi[a] = __shfl(ui[a], owner, 64);
   }
 }
 
