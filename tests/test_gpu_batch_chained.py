@@ -66,6 +66,16 @@ def test_chained_matches_separate_scan_and_oracle(torch_dev, oracle, slices):
     ch = native.BatchPlan(probs, slices_spin_half=half, slices_spin_one=one, chained=True)
     assert ch.workspace_size(True) == ch.workspace_size(False)
     assert ch.workspace_size(False) <= 256 + 128 * len(probs) + 256
+    if half and one:
+        # a unit is 64 / S groups of three consecutive intervals
+        units = 0
+        for p in probs:
+            S = half if p.spin_twice == 1 else one
+            while S > p.n_fine:
+                S >>= 1
+            span = 3 * (64 // S)
+            units += -(-p.n_samples // span)
+        assert ch.info()["n_items"] == units
     bs = _run(sep, store_u=True)
     bc = _run(ch, store_u=True)
     assert bool((bc["U"] == bs["U"]).all())
