@@ -20,12 +20,14 @@ def torch_dev():
 
 
 def _mixed_batch(seed):
-    """Both spins, lengths from one interval to several thousand work items'
-    worth (single-item simulations, exact multiples of 64 and ragged tails),
-    frame on and off, both method families and the full su(3) basis."""
+    """Both spins, lengths from one interval to several thousand units'
+    worth (single-unit simulations, exact multiples of 64 and of the 192
+    intervals of a one-slice unit, ragged tails), frame on and off, both
+    method families and the full su(3) basis."""
     rng = np.random.default_rng(seed)
     probs = []
-    for K in [1, 2, 63, 64, 65, 127, 128, 129, 1000, 4097, 70001]:
+    for K in [1, 2, 63, 64, 65, 127, 128, 129, 191, 192, 193, 383, 384, 385, 1000, 4097,
+              70001]:
         for spin_twice in (1, 2):
             probs.append(W.random_problem(rng, spin_twice, K, int(rng.integers(1, 9)),
                                           n_squares=int(rng.integers(8, 29)),
