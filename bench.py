@@ -43,14 +43,14 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 # the sources are unchanged.
 MEASURED_TRAFFIC = {
     ("mss_user_work_chained", "batched_sensing"): {
-        "src": "1d7bcaa999fe34cb",
-        "fetch_kib": 295194.3, "write_kib": 25472534.4,
-        "bytes": int(round((295194.3 * 2.000 + 25472534.4 * 1.000) * 1024)),
+        "src": "3cddbfb6a0a9c8eb",
+        "fetch_kib": 284383.0, "write_kib": 24306971.7,
+        "bytes": int(round((284383.0 * 2.000 + 24306971.7 * 1.000) * 1024)),
     },
     ("mss_user_work_integrate", "batched_sensing"): {
-        "src": "1d7bcaa999fe34cb",
-        "fetch_kib": 3723.7, "write_kib": 64036093.9,
-        "bytes": int(round((3723.7 * 2.000 + 64036093.9 * 1.000) * 1024)),
+        "src": "3cddbfb6a0a9c8eb",
+        "fetch_kib": 3700.7, "write_kib": 64036245.0,
+        "bytes": int(round((3700.7 * 2.000 + 64036245.0 * 1.000) * 1024)),
     },
 }
 

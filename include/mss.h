@@ -339,6 +339,12 @@ typedef struct mss_batch_options {
                                still written).  The workspace is then a 256-byte head plus 128
                                bytes per simulation, mss_batch_propagate is not available and
                                mss_batch_integrate needs U.  0: separate scan. */
+  int32_t chain_wait_us;    /* chained plans: bound of one unit's wait for the state the unit
+                               before leaves, in microseconds (0: 10 s, far beyond any real
+                               wait).  A wait that runs out marks the run failed: every later
+                               wait gives up at once, the launch drains its queue and ends, and
+                               mss_batch_check reports MSS_E_DEVICE (the states are then
+                               undefined).  Must be >= 0. */
 } mss_batch_options;
 
 typedef struct mss_batch_info_t {
@@ -393,6 +399,14 @@ mss_status mss_batch_propagate(mss_batch_plan* plan, const double* psi0, double*
                                double* psi_final, const double* U, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* Completion check of a chained plan's run: waits for `stream`, then reads
+ * the failure word the run keeps in the first bytes of `ws` (the workspace
+ * the run was given).  MSS_E_DEVICE when a wait ran out (see
+ * chain_wait_us) or a wave found lanes missing at its dequeue: the states
+ * of that run are undefined.  MSS_OK otherwise, and always for a
+ * separate-scan plan (which keeps no failure word). */
+mss_status mss_batch_check(const mss_batch_plan* plan, const void* ws, void* stream);
+
 /* Free the plan (its graph, stream and descriptors). */
 void mss_batch_plan_destroy(mss_batch_plan* plan);
 
@@ -406,7 +420,8 @@ void mss_batch_plan_destroy(mss_batch_plan* plan);
  * the sum of N_j over j < i, its states at the sum of K_j N_j, its
  * operators at the sum of K_j N_j^2 (complex units).  Synchronous: returns
  * once the outputs are written.  Errors as the plan calls, plus
- * MSS_E_NOMEM when the workspace cannot be allocated. */
+ * MSS_E_NOMEM when the workspace cannot be allocated and MSS_E_DEVICE when
+ * the run failed (mss_batch_check). */
 mss_status mss_solve_batch(int32_t n, const mss_problem* problems, const int64_t* param_off,
                            const double* params, const double* psi0, double* psi,
                            double* psi_final, double* U, void* stream);

@@ -4,6 +4,7 @@
 // the work-set layer (mss_work.h): the plan keeps the packed layout as
 // offsets and writes absolute pointers into the device descriptors when a
 // run brings new buffers.
+#include <stddef.h>
 #include <string.h>
 
 #include <algorithm>
@@ -122,8 +123,11 @@ mss_status user_function(mss_batch_plan* P, hipFunction_t* fn, bool chained = fa
 // The whole batch (integrate and scan, or one chained launch) or one half.
 hipError_t launch_batch(mss_batch_plan* P, bool integrate, bool scan, void* ws, hipFunction_t fn,
                         hipStream_t st) {
-  if (P->work.chained && integrate && scan)
-    return launch_work_chained(P->dev, ws, P->grid_blocks, st, fn);
+  if (P->work.chained && integrate && scan) {
+    const unsigned long long ticks =
+        P->opt.chain_wait_us ? 100ull * (unsigned long long)P->opt.chain_wait_us : kChainWaitTicks;
+    return launch_work_chained(P->dev, ws, P->grid_blocks, st, fn, ticks);
+  }
   hipError_t e = hipSuccess;
   if (integrate) e = launch_work_integrate(P->dev, (unsigned long long*)ws, P->grid_blocks, st, fn);
   if (e == hipSuccess && scan) e = launch_work_scan(P->dev, st);
@@ -160,6 +164,7 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
   if (opt.scan_per_lane != 0 && opt.scan_per_lane != 2 && opt.scan_per_lane != 4 &&
       opt.scan_per_lane != 8)
     return api_fail(MSS_E_INVALID, "scan_per_lane must be 0, 2, 4 or 8");
+  if (opt.chain_wait_us < 0) return api_fail(MSS_E_INVALID, "chain_wait_us must be >= 0");
   if (opt.chained != 0 && opt.chained != 1)
     return api_fail(MSS_E_INVALID, "chained must be 0 or 1");
   const int scan_e = opt.scan_per_lane ? opt.scan_per_lane : kScanPerLane;
@@ -378,6 +383,27 @@ mss_status mss_batch_propagate(mss_batch_plan* P, const double* psi0, double* ps
   return s == MSS_OK ? api_ok() : s;
 }
 
+mss_status mss_batch_check(const mss_batch_plan* P, const void* ws, void* stream) {
+  if (!P) return api_fail(MSS_E_INVALID, "plan is NULL");
+  if (!P->work.chained) return api_ok();
+  if (!ws) return api_fail(MSS_E_INVALID, "ws is NULL");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  unsigned long long failed = 0;
+  if (e == hipSuccess)
+    e = hipMemcpy(&failed, (const char*)ws + offsetof(ChainSync, failed), sizeof failed,
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return api_hip_fail(e, "chained run check");
+  if (failed == ~0ull)
+    return api_fail(MSS_E_DEVICE, "chained run failed: a wave reached its dequeue with lanes "
+                                  "missing; the states are undefined");
+  if (failed)
+    return api_fail(MSS_E_DEVICE,
+                    "chained run failed: unit %llu of a simulation waited longer than the "
+                    "bound for its entering state; the states are undefined",
+                    failed);
+  return api_ok();
+}
+
 void mss_batch_plan_destroy(mss_batch_plan* P) { release(P); }
 
 mss_status mss_solve_batch(int32_t n, const mss_problem* problems, const int64_t* param_off,
@@ -400,10 +426,7 @@ mss_status mss_solve_batch(int32_t n, const mss_problem* problems, const int64_t
                                    : api_hip_fail(e, "workspace allocation");
   }
   if (s == MSS_OK) s = mss_batch_run(P, params, psi0, psi, psi_final, U, ws, bytes, stream);
-  if (s == MSS_OK) {
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) s = api_hip_fail(e, "batch wait");
-  }
+  if (s == MSS_OK) s = mss_batch_check(P, ws, stream);  // waits for the run
   if (ws) (void)hipFree(ws);
   release(P);
   return s == MSS_OK ? api_ok() : s;

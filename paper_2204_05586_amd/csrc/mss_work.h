@@ -91,13 +91,15 @@ hipError_t launch_work_integrate(const DevWork& w, unsigned long long* counter, 
 // Enqueue the scan of every scanning sequence (reduce up, apply down).
 hipError_t launch_work_scan(const DevWork& w, hipStream_t st);
 
-// Enqueue a chained run of a chained work set: a reset kernel (item counter
-// to 0, call number + 1) and the persistent integrator that also forms the
-// states.  ws starts with a ChainSync block followed by one ChainSlot per
-// sequence (chain_workspace_bytes).  user_fn: the chained work integrator
-// of a user sampler's module, or null for the field-program kernel.
+// Enqueue a chained run of a chained work set: a reset kernel (unit counter,
+// failure word and every slot word to 0) and the persistent integrator that
+// also forms the states.  ws starts with a ChainSync block followed by one
+// ChainSlot per sequence (chain_workspace_bytes).  user_fn: the chained
+// work integrator of a user sampler's module, or null for the field-program
+// kernel.  wait_ticks: bound of one wait (100 MHz real-time counter).
 size_t chain_workspace_bytes(int32_t n_sims);
 hipError_t launch_work_chained(const DevWork& w, void* ws, int grid_blocks, hipStream_t st,
-                               hipFunction_t user_fn = nullptr);
+                               hipFunction_t user_fn = nullptr,
+                               unsigned long long wait_ticks = kChainWaitTicks);
 
 }  // namespace mss

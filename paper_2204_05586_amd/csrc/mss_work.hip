@@ -358,7 +358,7 @@ size_t chain_workspace_bytes(int32_t n_sims) {
 }
 
 hipError_t launch_work_chained(const DevWork& w, void* ws, int grid_blocks, hipStream_t st,
-                               hipFunction_t user_fn) {
+                               hipFunction_t user_fn, unsigned long long wait_ticks) {
   if (w.n_units == 0) return hipSuccess;
   ChainSync* sync = (ChainSync*)ws;
   const int64_t n_words = (int64_t)w.n_sims * (sizeof(ChainSlot) / sizeof(unsigned long long));
@@ -373,6 +373,7 @@ hipError_t launch_work_chained(const DevWork& w, void* ws, int grid_blocks, hipS
   a.order = w.order;
   a.slots = slots;
   a.sync = sync;
+  a.wait_ticks = wait_ticks;
   if (user_fn) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -59,8 +59,9 @@ struct IntegrateWorkArgs {
   unsigned long long* counter;
   int64_t n_items;
   int32_t n_sims;
-  // chained runs only (n_items then counts units of 64 / S intervals): the
-  // interleaved unit order and the chain slots.  Units go round by round
+  // chained runs only (n_items then counts units of kChainPerLane 64 / S
+  // intervals): the interleaved unit order, the chain slots and the bound
+  // of one wait (ticks of the 100 MHz real-time counter).  Units go round by round
   // (unit r of every simulation that has one, then unit r + 1, ...),
   // simulations within a round by decreasing unit count, so a round's
   // simulations are a prefix of `order`.  Rounds with the same simulation
@@ -73,6 +74,7 @@ struct IntegrateWorkArgs {
   const int32_t* order;         // [n_sims]
   ChainSlot* slots;             // [n_sims]
   ChainSync* sync;
+  unsigned long long wait_ticks;
 };
 
 __device__ __forceinline__ int64_t wave_broadcast(int64_t v) {
@@ -130,9 +132,9 @@ __device__ __forceinline__ void work_item(const IntegrateWorkArgs& A, const SimD
 // ---------------------------------------------------------------------------
 // chained runs
 // ---------------------------------------------------------------------------
-// Upper bound of one wait, in ticks of the 100 MHz real-time counter (10 s,
-// far beyond any real wait: a unit waits at most for the units dequeued
-// before it).
+// Default bound of one wait, in ticks of the 100 MHz real-time counter
+// (10 s, far beyond any real wait: a unit waits at most for the units
+// dequeued before it).
 constexpr unsigned long long kChainWaitTicks = 1000000000ull;
 
 // The current value of a word, read by an atomic compare-and-swap of 0
@@ -155,13 +157,14 @@ __device__ __forceinline__ bool wave_uniform(bool b) {
 
 // The state the unit with tag `tag` left in the slot (every lane receives
 // it): lanes 0 .. 4N - 1 hold one word each, v (read earlier), and read it
-// again until all carry the tag.  The loop's exits are wave-uniform.  false when the bound ran out, or a wait
-// of this run already had (then the kernel only drains its queue; the
-// states are undefined).
+// again until all carry the tag.  The loop's exits are wave-uniform.
+// Returns false when the wait ran past wait_ticks (it then writes its tag
+// into the failure word), or when a wait of this run already had (the
+// kernel then only drains its queue; the states are undefined).
 template <int N>
 __device__ __forceinline__ bool chain_receive(ChainSlot* slot, unsigned tag, ChainSync* sync,
-                                              int lane, unsigned long long v, double* xr,
-                                              double* xi) {
+                                              unsigned long long wait_ticks, int lane,
+                                              unsigned long long v, double* xr, double* xi) {
   const bool mine = lane < 4 * N;
   bool ok = true;
   const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
@@ -174,7 +177,7 @@ __device__ __forceinline__ bool chain_receive(ChainSlot* slot, unsigned tag, Cha
       ok = false;
       break;
     }
-    if (__builtin_amdgcn_s_memrealtime() - t0 > kChainWaitTicks) {
+    if (__builtin_amdgcn_s_memrealtime() - t0 > wait_ticks) {
       ok = false;
       if (lane == 0)
         (void)__hip_atomic_exchange(&sync->failed, (unsigned long long)tag, __ATOMIC_RELAXED,
@@ -331,7 +334,7 @@ __device__ __forceinline__ void chained_unit(const IntegrateWorkArgs& A, const S
       xi[a] = s.psi0[2 * a + 1];
     }
   } else {
-    (void)chain_receive<N>(slot, (unsigned)unit, A.sync, lane, early, xr, xi);
+    (void)chain_receive<N>(slot, (unsigned)unit, A.sync, A.wait_ticks, lane, early, xr, xi);
   }
   // y = P_j x: the state leaving group j; the one entering it is the group
   // before's leaving state (x for the first), and the parked operators

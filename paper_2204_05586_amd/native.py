@@ -27,7 +27,7 @@ EXPORTS = [
     "mss_workspace_size", "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
     "mss_solve", "mss_spin_projection", "mss_batch_plan_create", "mss_batch_layout", "mss_batch_workspace_size",
     "mss_batch_info", "mss_batch_run", "mss_batch_integrate", "mss_batch_propagate",
-    "mss_batch_plan_destroy", "mss_server_create", "mss_server_submit", "mss_server_poll",
+    "mss_batch_check", "mss_batch_plan_destroy", "mss_server_create", "mss_server_submit", "mss_server_poll",
     "mss_server_wait", "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
     "mss_server_clock", "mss_server_destroy", "mss_server_request_slices",
     "mss_adjoint_plan_create",
@@ -88,7 +88,8 @@ class Launch(C.Structure):
 class BatchOptions(C.Structure):
     _fields_ = [("slices_spin_half", C.c_int32), ("slices_spin_one", C.c_int32),
                 ("waves_per_simd", C.c_int32), ("use_graph", C.c_int32),
-                ("scan_per_lane", C.c_int32), ("chained", C.c_int32)]
+                ("scan_per_lane", C.c_int32), ("chained", C.c_int32),
+                ("chain_wait_us", C.c_int32)]
 
 
 class ServerOptions(C.Structure):
@@ -157,6 +158,7 @@ def lib() -> C.CDLL:
         L.mss_batch_run.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.mss_batch_integrate.argtypes = [vp, vp, vp, vp, sz, vp]
         L.mss_batch_propagate.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+        L.mss_batch_check.argtypes = [vp, vp, vp]
         L.mss_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(vp)]
         L.mss_server_submit.argtypes = [vp, PP, vp, vp, C.POINTER(C.c_uint64)]
         L.mss_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(RequestInfo)]
@@ -194,7 +196,8 @@ def lib() -> C.CDLL:
                      "mss_propagate_workspace_size", "mss_integrate", "mss_propagate",
                      "mss_solve", "mss_spin_projection", "mss_batch_plan_create", "mss_batch_layout",
                      "mss_batch_workspace_size", "mss_batch_info", "mss_batch_run",
-                     "mss_batch_integrate", "mss_batch_propagate", "mss_server_create",
+                     "mss_batch_integrate", "mss_batch_propagate", "mss_batch_check",
+                     "mss_server_create",
                      "mss_server_submit", "mss_server_poll", "mss_server_wait",
                      "mss_server_copy_out", "mss_server_release", "mss_server_stats_get",
                      "mss_adjoint_plan_create", "mss_adjoint_workspace_size",
@@ -500,11 +503,13 @@ class BatchPlan:
     the batch with it; otherwise the terms are interpreted.  The plan owns
     that sampler; ``specialized`` tells which happened.
     chained: ``run`` forms the states inside the integrator's launch (no
-    operator buffer, no scan; see mss_batch_options.chained)."""
+    operator buffer, no scan; see mss_batch_options.chained);
+    chain_wait_us bounds one unit's wait for its entering state (0: 10 s),
+    and ``check`` reports a run whose wait ran out."""
 
     def __init__(self, problems, slices_spin_half=0, slices_spin_one=0, waves_per_simd=0,
                  use_graph=False, scan_per_lane=0, sampler: "Optional[Sampler]" = None,
-                 specialize: bool = False, chained: bool = False):
+                 specialize: bool = False, chained: bool = False, chain_wait_us: int = 0):
         self.problems = list(problems)
         self._own_sampler = None
         self.specialized = False
@@ -526,11 +531,13 @@ class BatchPlan:
             self.param_off[:n] = np.concatenate([[0], np.cumsum(counts)[:-1]])
         self.n_params_total = int(counts.sum())
         opt = BatchOptions(int(slices_spin_half), int(slices_spin_one), int(waves_per_simd),
-                           int(bool(use_graph)), int(scan_per_lane), int(bool(chained)))
+                           int(bool(use_graph)), int(scan_per_lane), int(bool(chained)),
+                           int(chain_wait_us))
         self.options = {"slices_spin_half": int(slices_spin_half),
                         "slices_spin_one": int(slices_spin_one),
                         "waves_per_simd": int(waves_per_simd), "use_graph": bool(use_graph),
-                        "scan_per_lane": int(scan_per_lane), "chained": bool(chained)}
+                        "scan_per_lane": int(scan_per_lane), "chained": bool(chained),
+                        "chain_wait_us": int(chain_wait_us)}
         self.chained = bool(chained)
         h = C.c_void_p()
         offp = self.param_off.ctypes.data_as(C.POINTER(C.c_int64))
@@ -597,6 +604,11 @@ class BatchPlan:
         check(lib().mss_batch_propagate(self.handle, _ptr(bufs["psi0"]), _ptr(bufs["psi"]),
                                         _ptr(bufs["psi_final"]), _ptr(bufs["U"]), _ptr(ws),
                                         int(ws.numel()), _stream(stream)))
+
+    def check(self, bufs: dict, stream=None) -> None:
+        """mss_batch_check: waits for the stream and raises MssError when a
+        chained run failed (its states are then undefined)."""
+        check(lib().mss_batch_check(self.handle, _ptr(bufs["ws"]), _stream(stream)))
 
     def split(self, bufs: dict, i: int) -> dict:
         """Views of simulation i's outputs: psi [K, N], psi_final [N], U [K, N, N]."""

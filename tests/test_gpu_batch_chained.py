@@ -165,7 +165,8 @@ def test_chained_compiled_field_and_one_long_simulation(torch_dev, oracle):
 
 
 def test_chained_plan_api(torch_dev):
-    """A chained plan has no separate scan and keeps no operators."""
+    """A chained plan has no separate scan and keeps no operators; a normal
+    run passes mss_batch_check; a negative wait bound is refused."""
     from paper_2204_05586_amd import native
     probs = W.batched_sensing(n_sims=3, dur_lo=0.001, dur_hi=0.002)
     plan = native.BatchPlan(probs, chained=True)
@@ -174,7 +175,34 @@ def test_chained_plan_api(torch_dev):
         plan.propagate(bufs)
     with pytest.raises(native.MssError, match="needs U"):
         plan.integrate(bufs)
+    plan.run(bufs)
+    plan.check(bufs)  # a normal run passes its check
     plan.close()
+    with pytest.raises(native.MssInvalidError, match="chain_wait_us"):
+        native.BatchPlan(probs, chained=True, chain_wait_us=-1)
+
+
+def test_chained_wait_bound_reports_failure(torch_dev, oracle):
+    """A wait bound far below the real waits (one simulation: every unit
+    waits for the one before) makes the run give up: the launch still drains
+    and ends, and mss_batch_check reports the failure.  The same problem
+    without the bound checks clean and matches the oracle."""
+    from paper_2204_05586_amd import native
+    one = [W.spin_one_sensing(n_samples=20011, t_start=0.0495)]
+    bounded = native.BatchPlan(one, chained=True, chain_wait_us=1)
+    b = _run(bounded, store_u=False)
+    with pytest.raises(native.MssError, match="waited longer"):
+        bounded.check(b)
+    print(f"[gpu] bounded chained run reported: {native.last_error()}", flush=True)
+    bounded.close()
+    plain = native.BatchPlan(one, chained=True)
+    b = _run(plain, store_u=False)
+    plain.check(b)
+    ref = oracle.solve(one[0])
+    d = np.max(np.abs(plain.split(b, 0)["psi"].cpu().numpy() - ref["psi"]))
+    print(f"[gpu] unbounded run after it: check ok, max |d| vs oracle {d:.3e}", flush=True)
+    assert d <= TOL
+    plain.close()
 
 
 def test_one_shot_calls_match_plans(torch_dev, oracle):

@@ -151,6 +151,12 @@ def test_propagate_spin_requires_output():
     assert st == native.MSS_E_INVALID and "spin_twice" in native.last_error()
 
 
+def test_batch_check_rejects_a_null_plan():
+    """mss_batch_check validates its plan before any device call."""
+    st = native.lib().mss_batch_check(None, None, None)
+    assert st == native.MSS_E_INVALID and "plan" in native.last_error()
+
+
 def test_propagate_noalloc_checks_before_any_device_call():
     """Bad arguments and sizes beyond the static scratch are refused on the
     host (this container has no GPU, so any device call would fail)."""
