@@ -180,6 +180,15 @@ def test_chained_plan_api(torch_dev):
     plan.close()
     with pytest.raises(native.MssInvalidError, match="chain_wait_us"):
         native.BatchPlan(probs, chained=True, chain_wait_us=-1)
+    # unit tags are 32-bit: a simulation of 2^31 units or more is refused
+    # (before anything is allocated), one just below is planned
+    huge = W.spin_one_sensing(n_samples=2 ** 39)
+    with pytest.raises(native.MssError, match="too long for a chained plan"):
+        native.BatchPlan([huge], chained=True, slices_spin_one=1)
+    ok = native.BatchPlan([W.spin_one_sensing(n_samples=192 * (2 ** 31 - 1))], chained=True,
+                          slices_spin_one=1)
+    assert ok.info()["n_items"] == 2 ** 31 - 1
+    ok.close()
 
 
 def test_chained_wait_bound_reports_failure(torch_dev, oracle):
