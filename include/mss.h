@@ -326,7 +326,8 @@ typedef struct mss_batch_plan mss_batch_plan;
 typedef struct mss_batch_options {
   int32_t slices_spin_half; /* lanes per spin-1/2 interval, power of two <= 64, 0: choose */
   int32_t slices_spin_one;  /* lanes per spin-1 interval, 0: choose */
-  int32_t waves_per_simd;   /* persistent grid: resident waves per SIMD (0: 2) */
+  int32_t waves_per_simd;   /* persistent grid: resident waves per SIMD (0: 2; chained
+                               plans take at most the two a CU holds) */
   int32_t use_graph;        /* 1: capture the batch as one HIP graph, replayed while the
                                buffer pointers stay the same */
   int32_t scan_per_lane;    /* operators per lane in the scan tiles: 2, 4 or 8 (0: 4) */

@@ -243,7 +243,19 @@ mss_status create_plan(int32_t n, const mss_problem* problems, const int64_t* pa
   }
   P->dev = device_view(P->work, (const char*)P->desc, P->o_sims, P->o_terms, P->o_reduce,
                        P->o_apply, P->o_chain);
-  const int wps = opt.waves_per_simd ? opt.waves_per_simd : 2;
+  int wps = opt.waves_per_simd ? opt.waves_per_simd : 2;
+  if (P->work.chained) {
+    // a CU holds as many chained workgroups as its LDS has room for their
+    // parked operators (two on gfx950, which their registers also allow); a
+    // workgroup beyond those would only start once the queue is drained
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess) {
+      const int fit = lds / (int)(4 * kChainParkDoubles * sizeof(double));
+      if (fit > 0) wps = std::min(wps, fit);
+    }
+  }
   const int64_t blocks = (int64_t)cu * wps;  // 256-thread blocks: one wave per SIMD each
   const int64_t units = P->work.chained ? P->work.n_units : P->work.n_items;
   P->grid_blocks = (int)std::max<int64_t>(1, std::min(blocks, (units + 3) / 4));

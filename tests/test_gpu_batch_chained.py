@@ -180,6 +180,17 @@ def test_chained_plan_api(torch_dev):
     plan.close()
     with pytest.raises(native.MssInvalidError, match="chain_wait_us"):
         native.BatchPlan(probs, chained=True, chain_wait_us=-1)
+    # a CU holds two chained workgroups: a plan asking for four per CU launches
+    # two, and still gives the states the default plan gives
+    cu = torch_dev.cuda.get_device_properties(0).multi_processor_count
+    many = W.batched_sensing(n_sims=2 * cu, dur_lo=0.002, dur_hi=0.004)
+    four = native.BatchPlan(many, chained=True, waves_per_simd=4)
+    two = native.BatchPlan(many, chained=True)
+    assert four.info()["grid_blocks"] == two.info()["grid_blocks"] == 2 * cu
+    b4, b2 = _run(four, store_u=False), _run(two, store_u=False)
+    assert torch_dev.equal(b4["psi"], b2["psi"])
+    four.close()
+    two.close()
     # unit tags are 32-bit: a simulation of 2^31 units or more is refused
     # (before anything is allocated), one just below is planned
     huge = W.spin_one_sensing(n_samples=2 ** 39)
