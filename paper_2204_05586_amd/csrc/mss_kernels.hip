@@ -102,6 +102,11 @@ __global__ void __launch_bounds__(64 * kTopWaves) scan_top_kernel(const double* 
   if (lane == 0) set_identity<N>(X);
   double vr[N], vi[N];
   matvec<N>(X, xr, xi, vr, vi);
+  // the lane's elements but its last, all loaded before the first product
+  Mat<N> Y[E - 1];
+#pragma unroll
+  for (int e = 0; e < E - 1; ++e)
+    if (base + e < n1) load_mat<N>(M1 + (size_t)(base + e) * 2 * N * N, Y[e]);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int64_t idx = base + e;
@@ -113,10 +118,8 @@ __global__ void __launch_bounds__(64 * kTopWaves) scan_top_kernel(const double* 
         o[2 * a + 1] = vi[a];
       }
       if (e + 1 < E) {
-        Mat<N> Y;
-        load_mat<N>(M1 + (size_t)idx * 2 * N * N, Y);
         double wr_[N], wi_[N];
-        matvec<N>(Y, vr, vi, wr_, wi_);
+        matvec<N>(Y[e < E - 1 ? e : 0], vr, vi, wr_, wi_);
 #pragma unroll
         for (int a = 0; a < N; ++a) {
           vr[a] = wr_[a];

@@ -187,7 +187,8 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
 // The state entering element w of a sequence of n <= 64 E elements that
 // starts from `start` (every lane gets it): what tile_apply writes for
 // element w of tile 0, by the same operations (scan, the lane's prefix
-// applied to start, its walk up to w).  Every lane must call this.
+// applied to start, its walk up to w).  The lane's elements stay in
+// registers from the scan to the walk.  Every lane must call this.
 template <int N, int E>
 __device__ __forceinline__ void single_tile_state(const double* __restrict__ M, int64_t n,
                                                   int64_t w, int lane,
@@ -195,7 +196,8 @@ __device__ __forceinline__ void single_tile_state(const double* __restrict__ M, 
                                                   double* vi) {
   const int64_t base = (int64_t)lane * E;
   Mat<N> P;
-  lane_product<N, E>(M, n, base, P);
+  Mat<N> kept[E];
+  lane_product_keep<N, E>(M, n, base, P, kept);
   wave_scan<N>(lane, lanes_with_data<E>(n, 0), P);
   Mat<N> X = shfl_up_mat<N>(P, 1);
   if (lane == 0) set_identity<N>(X);
@@ -209,17 +211,19 @@ __device__ __forceinline__ void single_tile_state(const double* __restrict__ M, 
   matvec<N>(X, sr, si, ur, ui);
   const int owner = (int)(w / E);
   const int steps = (int)(w % E);
-  for (int e = 0; e < steps; ++e) {  // wave-uniform count
-    Mat<N> Y;
-    const int64_t idx = base + e;
-    if (idx < n) load_mat<N>(M + (size_t)idx * 2 * N * N, Y);
-    else set_identity<N>(Y);
-    double wr_[N], wi_[N];
-    matvec<N>(Y, ur, ui, wr_, wi_);
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
-      ur[a] = wr_[a];
-      ui[a] = wi_[a];
+  for (int e = 0; e < E - 1; ++e) {
+    if (e < steps) {  // wave-uniform
+      Mat<N> Y;
+      if (base + e < n) Y = kept[e];
+      else set_identity<N>(Y);
+      double wr_[N], wi_[N];
+      matvec<N>(Y, ur, ui, wr_, wi_);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        ur[a] = wr_[a];
+        ui[a] = wi_[a];
+      }
     }
   }
 #pragma unroll
