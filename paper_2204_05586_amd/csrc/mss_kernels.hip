@@ -42,9 +42,11 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const double* __restric
 }
 
 // Level 0 of a one-level scan (n1 <= kScanTile tile aggregates A1) with the
-// top level folded in: each wave forms the state entering its tile from
-// start as the level-1 apply would (single_tile_state, the same operations),
-// then applies its tile.  Bitwise the result of the two launches.
+// top level folded in: each wave scans its tile (its operators kept in
+// registers), forms the state entering its tile from start as the level-1
+// apply would (single_tile_state, the same operations), then walks its tile.
+// Bitwise the result of the two launches.  The tile's loads are issued
+// first, so their latency overlaps the level-1 work.
 template <int N>
 __global__ void __launch_bounds__(256) scan_apply_fold_kernel(const double* __restrict__ M,
                                                               int64_t n,
@@ -54,13 +56,18 @@ __global__ void __launch_bounds__(256) scan_apply_fold_kernel(const double* __re
                                                               double* __restrict__ before,
                                                               double* __restrict__ after_last,
                                                               double* __restrict__ spin) {
+  constexpr int E = kScanPerLane;
   const int lane = threadIdx.x & 63;
   const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const bool valid = tile < n1;
+  const int64_t base = tile * kScanTile + (int64_t)lane * E;
+  Mat<N> P;
+  Mat<N> kept[E];
+  lane_product_keep<N, E>(M, n, base, P, kept);
+  wave_scan<N>(lane, lanes_with_data<E>(n, tile), P);
   double sr[N], si[N];
-  single_tile_state<N, kScanPerLane>(A1, n1, valid ? tile : 0, lane, start, sr, si);
-  tile_apply<N, kScanPerLane, true>(M, n, tile, lane, valid, nullptr, before, after_last, spin,
-                                    sr, si);
+  single_tile_state<N, E>(A1, n1, valid ? tile : 0, lane, start, sr, si);
+  tile_walk<N, E, true>(P, kept, M, n, base, lane, valid, sr, si, before, after_last, spin);
 }
 
 // Levels 1 and 2 of a two-level scan in one workgroup (n1 <= kTopWaves tiles of

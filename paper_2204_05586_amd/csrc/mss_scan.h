@@ -116,42 +116,23 @@ __device__ __forceinline__ void tile_reduce(const double* __restrict__ M, int64_
   if (lane == L - 1 && agg_out) store_mat<N>(agg_out, P);
 }
 
-// Tile apply: before[i] = M[i-1] ... M[tT] start for i in tile t (the state
-// entering element i); after_last (optional) receives M[n-1] ... applied
-// when the tile holds the last element; spin (optional, [n][3]) receives
-// <J_x>, <J_y>, <J_z> of every state written.  The start state is read from
-// start, or (start null) taken from start_r / start_i in registers.  Every
-// lane must call this.
-// KEEP: the lane's matrices stay in registers from the scan to the walk
-// (one read of M instead of two); the values and operations are the same.
-template <int N, int E, bool KEEP = false>
-__device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t n, int64_t tile,
-                                           int lane, bool valid, const double* __restrict__ start,
-                                           double* __restrict__ before,
-                                           double* __restrict__ after_last,
-                                           double* __restrict__ spin = nullptr,
-                                           const double* start_r = nullptr,
-                                           const double* start_i = nullptr) {
-  const int64_t base = tile * (64 * E) + (int64_t)lane * E;
-  Mat<N> P;
-  Mat<N> kept[KEEP ? E : 1];
-  if constexpr (KEEP) lane_product_keep<N, E>(M, n, base, P, kept);
-  else lane_product<N, E>(M, n, base, P);
-  wave_scan<N>(lane, lanes_with_data<E>(n, tile), P);
+// The walk of tile_apply: from the lane's inclusive product P (its Q_j on
+// the scan's entry; kept[] its matrices when KEEP), the state entering the
+// lane's first element is P_{lane-1} start (start for lane 0), carried
+// through its elements; writes before[idx] (and spin, after_last) for the
+// lane's elements base .. base + E - 1 below n.  Every lane must call this.
+template <int N, int E, bool KEEP>
+__device__ __forceinline__ void tile_walk(const Mat<N>& P, const Mat<N> (&kept)[KEEP ? E : 1],
+                                          const double* __restrict__ M, int64_t n, int64_t base,
+                                          int lane, bool valid, const double* sr,
+                                          const double* si, double* __restrict__ before,
+                                          double* __restrict__ after_last,
+                                          double* __restrict__ spin) {
   Mat<N> X = shfl_up_mat<N>(P, 1);
   if (lane == 0) set_identity<N>(X);
   if (!valid) return;
-  // v = X start
   double vr[N], vi[N];
-  {
-    double sr[N], si[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-      sr[a] = start ? start[2 * a] : start_r[a];
-      si[a] = start ? start[2 * a + 1] : start_i[a];
-    }
-    matvec<N>(X, sr, si, vr, vi);
-  }
+  matvec<N>(X, sr, si, vr, vi);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int64_t idx = base + e;
@@ -182,6 +163,33 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
       }
     }
   }
+}
+
+// Tile apply: before[i] = M[i-1] ... M[tT] start for i in tile t (the state
+// entering element i); after_last (optional) receives M[n-1] ... applied
+// when the tile holds the last element; spin (optional, [n][3]) receives
+// <J_x>, <J_y>, <J_z> of every state written.  Every lane must call this.
+// KEEP: the lane's matrices stay in registers from the scan to the walk
+// (one read of M instead of two); the values and operations are the same.
+template <int N, int E, bool KEEP = false>
+__device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t n, int64_t tile,
+                                           int lane, bool valid, const double* __restrict__ start,
+                                           double* __restrict__ before,
+                                           double* __restrict__ after_last,
+                                           double* __restrict__ spin = nullptr) {
+  const int64_t base = tile * (64 * E) + (int64_t)lane * E;
+  Mat<N> P;
+  Mat<N> kept[KEEP ? E : 1];
+  if constexpr (KEEP) lane_product_keep<N, E>(M, n, base, P, kept);
+  else lane_product<N, E>(M, n, base, P);
+  wave_scan<N>(lane, lanes_with_data<E>(n, tile), P);
+  double sr[N], si[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    sr[a] = valid ? start[2 * a] : 0.0;
+    si[a] = valid ? start[2 * a + 1] : 0.0;
+  }
+  tile_walk<N, E, KEEP>(P, kept, M, n, base, lane, valid, sr, si, before, after_last, spin);
 }
 
 // The state entering element w of a sequence of n <= 64 E elements that
