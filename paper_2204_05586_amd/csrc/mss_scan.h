@@ -178,17 +178,18 @@ __device__ __forceinline__ void tile_apply(const double* __restrict__ M, int64_t
                                            double* __restrict__ after_last,
                                            double* __restrict__ spin = nullptr) {
   const int64_t base = tile * (64 * E) + (int64_t)lane * E;
-  Mat<N> P;
-  Mat<N> kept[KEEP ? E : 1];
-  if constexpr (KEEP) lane_product_keep<N, E>(M, n, base, P, kept);
-  else lane_product<N, E>(M, n, base, P);
-  wave_scan<N>(lane, lanes_with_data<E>(n, tile), P);
+  // the entering state is read first, so its latency overlaps the scan's
   double sr[N], si[N];
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     sr[a] = valid ? start[2 * a] : 0.0;
     si[a] = valid ? start[2 * a + 1] : 0.0;
   }
+  Mat<N> P;
+  Mat<N> kept[KEEP ? E : 1];
+  if constexpr (KEEP) lane_product_keep<N, E>(M, n, base, P, kept);
+  else lane_product<N, E>(M, n, base, P);
+  wave_scan<N>(lane, lanes_with_data<E>(n, tile), P);
   tile_walk<N, E, KEEP>(P, kept, M, n, base, lane, valid, sr, si, before, after_last, spin);
 }
 
