@@ -181,16 +181,25 @@ def test_chained_plan_api(torch_dev):
     with pytest.raises(native.MssInvalidError, match="chain_wait_us"):
         native.BatchPlan(probs, chained=True, chain_wait_us=-1)
     # a CU holds two chained workgroups: a plan asking for four per CU launches
-    # two, and still gives the states the default plan gives
+    # two, and one asking for one launches one; all give the same states
     cu = torch_dev.cuda.get_device_properties(0).multi_processor_count
     many = W.batched_sensing(n_sims=2 * cu, dur_lo=0.002, dur_hi=0.004)
     four = native.BatchPlan(many, chained=True, waves_per_simd=4)
     two = native.BatchPlan(many, chained=True)
+    one = native.BatchPlan(many, chained=True, waves_per_simd=1)
     assert four.info()["grid_blocks"] == two.info()["grid_blocks"] == 2 * cu
+    assert one.info()["grid_blocks"] == cu
     b4, b2 = _run(four, store_u=False), _run(two, store_u=False)
     assert torch_dev.equal(b4["psi"], b2["psi"])
+    # one workgroup per CU: every resident wave goes round the queue more
+    # often; units still wait only for units taken before them
+    b1 = _run(one, store_u=False)
+    one.check(b1)
+    assert torch_dev.equal(b1["psi"], b2["psi"])
+    assert torch_dev.equal(b1["psi_final"], b2["psi_final"])
     four.close()
     two.close()
+    one.close()
     # unit tags are 32-bit: a simulation of 2^31 units or more is refused
     # (before anything is allocated), one just below is planned
     huge = W.spin_one_sensing(n_samples=2 ** 39)
