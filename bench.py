@@ -130,6 +130,29 @@ def cpu_baseline(problems, seconds: float) -> dict:
             "host": {"cpu_count": os.cpu_count(), "model": _cpu_model()}}
 
 
+def cpu_serving_baseline(seconds: float) -> dict:
+    """The CPU oracle on the serving workload's requests (the 10 req/s
+    stream, in arrival order), solved one after another for a bounded
+    time: the rate a CPU server would sustain on the same mix."""
+    from oracle import oracle
+    from paper_2204_05586_amd import workloads as W
+    stream = W.serving_stream(10.0, n_requests=600, rate_index=0)
+    threads = oracle.get_threads()
+    steps, used, t0 = 0, 0, time.perf_counter()
+    for r in stream:
+        oracle.solve(r.problem)
+        steps += r.problem.fine_steps
+        used += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(steps / dt, 1), "unit": "fine_steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"the first {used} of the 10 req/s stream's {len(stream)} requests in "
+                      f"arrival order ({steps} fine steps, {dt:.1f} s, {threads} OpenMP threads "
+                      f"over intervals)"}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -735,6 +758,8 @@ def main():
 
     base = (cpu_baseline(base_problems, args.cpu_baseline_seconds)
             if args.cpu_baseline_seconds > 0 else None)
+    if base is not None and serving is not None:
+        base["serving"] = cpu_serving_baseline(args.cpu_baseline_seconds / 3)
 
     out = {
         "metric": "CF4 fine steps/sec (spin-1, FP64) batched vs plain on 1 GPU; p50/p99 latency",

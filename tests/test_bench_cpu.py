@@ -39,3 +39,14 @@ def test_traffic_table_names_kernels_the_bench_reports():
         assert workload == "batched_sensing"
         assert v["bytes"] == int(round((v["fetch_kib"] * 2.0 + v["write_kib"]) * 1024))
         assert len(v["src"]) == 16
+
+
+def test_cpu_serving_baseline_solves_the_request_stream_in_order():
+    """The oracle's serving sample: the 10 req/s stream's requests from the
+    first, one after another, until the time bound passes."""
+    from paper_2204_05586_amd import workloads as W
+    r = bench.cpu_serving_baseline(0.05)
+    first = W.serving_stream(10.0, n_requests=600, rate_index=0)[0].problem.fine_steps
+    assert r["kind"] == "oracle" and r["unit"] == "fine_steps/s" and r["value"] > 0
+    assert r["sample"].startswith("the first 1 of the 10 req/s stream's 600 requests")
+    assert f"({first} fine steps" in r["sample"]
