@@ -239,6 +239,32 @@ def bench_plain(prob, steps: int, warmup: int, specialise: bool = True) -> dict:
             "launch": {"slices": launch[0], "block": launch[1]}, "tau": prob.n_squares}
 
 
+def states_to_host(psi, stream, max_bytes: int = 2 << 30) -> dict:
+    """The states' copy to the host, outside every timed step: a prefix of
+    at most max_bytes into pinned host memory (allocated pinned), three
+    copies between HIP events; the rate and the time it gives for all the
+    states."""
+    import torch
+    flat = psi.view(-1)
+    n = min(flat.numel(), max_bytes // flat.element_size())
+    host = torch.empty(n, dtype=flat.dtype, pin_memory=True)
+    ms = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        with torch.cuda.stream(stream):
+            host.copy_(flat[:n], non_blocking=True)
+        b.record(stream)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    nbytes = n * flat.element_size()
+    rate = nbytes / (min(ms) * 1e-3)
+    total = flat.numel() * flat.element_size()
+    del host
+    return {"bytes": nbytes, "ms": round(min(ms), 3), "gb_per_s": round(rate / 1e9, 2),
+            "states_bytes": total, "states_ms_at_that_rate": round(total / rate * 1e3, 1)}
+
+
 def bench_batched(problems, steps: int, warmup: int, tune: bool, specialise: bool = True,
                   separate_reps: int = 3) -> dict:
     """The batch as one captured HIP graph of a chained plan (the shared
@@ -285,6 +311,7 @@ def bench_batched(problems, steps: int, warmup: int, tune: bool, specialise: boo
     specialized = plan.specialized
     ws_bytes = int(bufs["ws"].numel())
     psi_chained = bufs["psi"]
+    d2h = states_to_host(psi_chained, stream)
     plan.close()
     del bufs["ws"]
     # the separate-scan plan: integrator then scan, eager
@@ -321,7 +348,7 @@ def bench_batched(problems, steps: int, warmup: int, tune: bool, specialise: boo
             "replay_ms_mean": statistics.mean(replay),
             "replay_ms_median": statistics.median(replay),
             "replay_ms_min": min(replay), "replay_ms_max": max(replay),
-            "workspace_bytes": ws_bytes,
+            "workspace_bytes": ws_bytes, "d2h": d2h,
             "separate_scan": {"integrate_ms": statistics.mean(integ),
                               "propagate_ms": statistics.mean(prop),
                               "ms_per_step": statistics.mean(integ) + statistics.mean(prop),
@@ -689,6 +716,7 @@ def main():
                  "replay_ms_median": round(res["replay_ms_median"], 3),
                  "replay_ms_min": round(res["replay_ms_min"], 3),
                  "replay_ms_max": round(res["replay_ms_max"], 3),
+                 "d2h": res["d2h"],
                  "separate_scan": {k: (round(v, 3) if isinstance(v, float) and k.endswith("ms")
                                        else v) for k, v in sep.items()},
                  "integrate_ms_interpreter": round(res["integrate_ms_interpreter"], 3),
