@@ -217,7 +217,18 @@ mss_status resolve_launch(const mss_problem* p, const mss_launch* in, int* slice
   int S = in ? in->slices : 0;
   if (given) *given = S != 0;
   int B = in ? in->block : 0;
-  if (S == 0) S = plan_slices(p->n_samples, p->n_fine, device_cu_count());
+  const int cu = device_cu_count();
+  if (S == 0) S = plan_slices(p->n_samples, p->n_fine, cu);
+  if (B == 0 && S >= 1 && S <= 64) {
+    // a launch of at most 3 waves per SIMD in all runs its waves at once;
+    // one-wave workgroups then spread them evenly over the CUs (four-wave
+    // workgroups leave some CUs a workgroup more than others: spin-1/2 1e4
+    // intervals at 16 slices, 2,500 waves, 19.0 -> 18.5 us).  Longer
+    // launches keep 256-lane workgroups, the fastest in a sweep of the
+    // 2e5-interval spin-1 simulation.
+    const int64_t waves = (p->n_samples * S + 63) / 64;
+    B = waves <= 3 * 4 * (int64_t)cu ? 64 : 256;
+  }
   if (B == 0) B = 256;
   if (S < 1 || S > 64 || (S & (S - 1)) != 0 || S > p->n_fine)
     return api_fail(MSS_E_INVALID, "launch.slices must be a power of two in [1, min(64, L)], got %d",
