@@ -97,6 +97,18 @@ def test_launch_plan_is_valid():
         assert B in (64, 128, 256)
 
 
+def test_launch_plan_block_follows_the_wave_count():
+    """Launches of at most 3 waves per SIMD (a 256-CU device when none is
+    visible: 3072 waves) take one-wave workgroups, longer ones 256 lanes;
+    a given block is kept."""
+    half = W.spin_half_rabi()                       # 1e4 intervals x 16 slices: 2,500 waves
+    assert native.plan_launch(half) == (16, 64)
+    assert native.plan_launch(W.spin_one_sensing()) == (2, 256)   # 6,250 waves
+    big = W.spin_half_rabi(n_samples=200_000)
+    S, B = native.plan_launch(big)
+    assert B == (64 if (big.n_samples * S + 63) // 64 <= 3072 else 256)
+
+
 def test_solve_requires_buffers():
     prob = W.spin_half_rabi(n_samples=4)
     pk = native.PackedProblem(prob)
